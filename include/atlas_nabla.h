@@ -1,0 +1,260 @@
+/*
+ * atlas_nabla.h -- C ABI of the MI355X (gfx950) median-dual Nabla library.
+ *
+ * The calls follow the Grid -> Mesh -> FunctionSpace -> Field workflow of the
+ * Atlas report (Section 2.3, Figure 2): a mesh is built once from a grid
+ * name, fields are plain device arrays laid out as NodeColumns (one column of
+ * levels per mesh node), and the Nabla operators the report lists among the
+ * operations Atlas supplies (gradient, divergence, Laplacian; Section 2.3)
+ * are applied to them.  The report's own language bindings wrap each C++
+ * method in one C function taking plain pointers (Section 4.1, Figure 3);
+ * this header keeps that pattern: only C types, plain host or device
+ * pointers and sizes cross it, and no C++ exception escapes.
+ *
+ * Conventions for every call
+ *   - Return value: ATLAS_OK (0) or a negative status below.  On failure the
+ *     thread-local message of atlas_last_error() says why.  Argument errors
+ *     are detected synchronously, before anything is launched.
+ *   - Fields are dense, contiguous, row-major device arrays:
+ *       scalar  [nnodes][nlev]        (levels innermost)
+ *       vector  [nnodes][nlev][2]     (east, north components innermost)
+ *     Element type is given by atlas_dtype_t.  Pointers must be aligned to
+ *     the element size (scalars) or twice the element size (vectors).
+ *   - Outputs are overwritten, never accumulated into; an output may not
+ *     overlap its input (the operators gather neighbour values).
+ *   - `stream` is a hipStream_t of the mesh's device passed as void*
+ *     (NULL = the default stream).  Operator calls are asynchronous on it.
+ *   - Node order, edge order and the dual geometry are defined by
+ *     atlas_mesh_build; see the comment there.
+ */
+#ifndef ATLAS_NABLA_H
+#define ATLAS_NABLA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ATLAS_NABLA_ABI_VERSION 1
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+  ATLAS_OK = 0,
+  ATLAS_EINVAL = -1,  /* bad argument: NULL, bad name, misaligned, overlap  */
+  ATLAS_ENOMEM = -2,  /* host or device allocation failed                  */
+  ATLAS_EHIP = -3,    /* a HIP runtime call or kernel launch failed        */
+  ATLAS_ENODEV = -4,  /* no GPU, bad device ordinal, or a host-only mesh   */
+  ATLAS_EDTYPE = -5,  /* unknown dtype, or dtype not supported by the call */
+  ATLAS_ESHAPE = -6   /* nlev <= 0, or sizes beyond the supported range    */
+};
+
+/* ---- element types ----------------------------------------------------- */
+typedef enum {
+  ATLAS_F64 = 0,  /* FP64 storage and arithmetic, FP64 geometry tables      */
+  ATLAS_F32 = 1,  /* FP32 storage and arithmetic; tables rounded once from
+                     the FP64 geometry                                      */
+  ATLAS_BF16 = 2  /* bfloat16 storage, FP32 arithmetic, FP32 tables; each
+                     output is rounded to nearest-even bfloat16             */
+} atlas_dtype_t;
+
+typedef struct atlas_mesh_s* atlas_mesh_t;
+
+/* Static version string, e.g. "atlas-nabla 0.1.0 gfx950". */
+const char* atlas_version(void);
+
+/* Message for the last non-OK status returned on this thread ("" if none).
+ * The pointer stays valid until the next failing call on the thread. */
+const char* atlas_last_error(void);
+
+/* Number of visible HIP devices.  Returns ATLAS_ENODEV (and *count = 0) when
+ * the HIP runtime reports none. */
+int atlas_device_count(int* count);
+
+/* ---- mesh ---------------------------------------------------------------- */
+
+/* Build the median-dual mesh of an octahedral reduced Gaussian grid.
+ *
+ * grid    "O<N>", N >= 1 (the report names grids this way, Section 4.3).
+ *         Row k (0..2N-1, north to south) lies at the k-th Gaussian
+ *         colatitude (root of P_2N(cos t)) and holds 4*min(k+1, 2N-k)+16
+ *         points at longitudes 2*pi*j/n_k; nodes are numbered row by row.
+ *         Bands between rows are triangulated by an exact-integer zipper,
+ *         each 20-point polar row by a ladder of 18 triangles whose 17
+ *         chords are the pole edges; no node sits at a pole.
+ *         V = 4N^2 + 36N nodes, E = 3V - 6 edges, T = 2V - 4 triangles.
+ * radius  sphere radius in metres (> 0), e.g. 6371220.0.
+ * device  HIP device ordinal that receives the operator tables, or -1 for a
+ *         host-only mesh (connectivity and geometry only: the export calls
+ *         work, operator calls return ATLAS_ENODEV).
+ * out     receives the handle; the library owns all its memory until
+ *         atlas_mesh_free.
+ * Errors: ATLAS_EINVAL (name, radius, NULL out), ATLAS_ENODEV (no such
+ * device), ATLAS_ENOMEM, ATLAS_EHIP, ATLAS_ESHAPE (N too large for 32-bit
+ * node indices). */
+int atlas_mesh_build(const char* grid, double radius, int device, atlas_mesh_t* out);
+
+/* Release host and device memory of a mesh.  NULL is allowed.  The caller
+ * must make sure no queued operator call still uses the mesh. */
+void atlas_mesh_free(atlas_mesh_t mesh);
+
+/* Sizes.  Any output pointer may be NULL.  max_slots is the largest node
+ * degree (<= 7); nrows = 2N. */
+int atlas_mesh_sizes(atlas_mesh_t mesh, int64_t* nnodes, int64_t* nedges,
+                     int64_t* ntris, int64_t* npole_edges, int32_t* max_slots,
+                     int32_t* nrows);
+
+/* Host copies of the grid.  Caller-owned host buffers; any may be NULL.
+ * row_size [nrows], row_off [nrows+1], colat [nrows] (radians),
+ * lonlat [V][2] (radians), xyz [V][3] (unit sphere). */
+int atlas_mesh_export_grid(atlas_mesh_t mesh, int32_t* row_size, int64_t* row_off,
+                           double* colat, double* lonlat, double* xyz);
+
+/* Host copies of the connectivity.  Caller-owned host buffers; any may be
+ * NULL.  tris [T][3] (counter-clockwise seen from outside, smallest index
+ * first, list sorted), edges [E][2] (a < b, sorted), csr_off [V+1],
+ * nbr/eid [2E] (slots of each node ordered by neighbour index), sgn [2E]
+ * (+1 if the node is the edge's first end, -1 otherwise), rev [2E] (position
+ * of the node in its neighbour's slot list), is_pole [E] (1 for ladder
+ * chords). */
+int atlas_mesh_export_connectivity(atlas_mesh_t mesh, int32_t* tris, int32_t* edges,
+                                   int64_t* csr_off, int32_t* nbr, int32_t* eid,
+                                   int8_t* sgn, int8_t* rev, uint8_t* is_pole);
+
+/* Host copies of the FP64 median-dual geometry.  Caller-owned host buffers;
+ * any may be NULL.  S [E][3] dual normal of each edge in metres (integrated
+ * outward conormal of the dual face, pointing from the edge's first end to
+ * its second), V [V] dual cell areas in m^2, basis [V][2][3] local (east,
+ * north) unit vectors, C [V][3] closure sum_e sign(i,e) S_e. */
+int atlas_mesh_export_geometry(atlas_mesh_t mesh, double* S, double* V,
+                               double* basis, double* C);
+
+/* ---- operators ------------------------------------------------------------
+ * All five are gathers over each node's edges (no atomics): every output
+ * element is written by exactly one thread in a fixed slot order, so reruns
+ * are bitwise identical.  Units follow the radius: gradient and divergence
+ * per metre, Laplacian per square metre. */
+
+/* grad_i = (1/V_i) [sum_e sign(i,e) 0.5 (f_i + f_j) S_e - f_i C_i], projected
+ * on (east_i, north_i); evaluated in the equivalent difference form
+ * sum_e sign(i,e) 0.5 (f_j - f_i) S_e / V_i.
+ * f: scalar [V][nlev] -> grad: vector [V][nlev][2]. */
+int atlas_nabla_gradient(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                         const void* f, void* grad, void* stream);
+
+/* div_i = (1/V_i) sum_e sign(i,e) 0.5 (U_i + U_j) . S_e with
+ * U = u east + v north.  uv: vector [V][nlev][2] -> div: scalar [V][nlev]. */
+int atlas_nabla_divergence(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                           const void* uv, void* div, void* stream);
+
+/* lap = div(grad f).  f, lap: scalar [V][nlev].
+ * workspace == NULL: one fused pass over the precomputed two-ring stencil
+ *   lap_i = sum_m W_im (f_m - f_i), W = (divergence matrix)(gradient matrix).
+ * workspace != NULL: two passes through a caller-owned device buffer of
+ *   V*nlev*2 elements of the dtype (gradient, then divergence). */
+int atlas_nabla_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                          const void* f, void* lap, void* workspace, void* stream);
+
+/* Exact transpose of atlas_nabla_gradient for the plain Euclidean inner
+ * product over all (node, level, component) entries:
+ * sum(w * grad f) == sum(f * gradient_adjoint(w)).
+ * w: vector [V][nlev][2] -> fbar: scalar [V][nlev]. */
+int atlas_nabla_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                 const void* w, void* fbar, void* stream);
+
+/* Exact transpose of atlas_nabla_divergence.
+ * d: scalar [V][nlev] -> uvbar: vector [V][nlev][2]. */
+int atlas_nabla_divergence_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                   const void* d, void* uvbar, void* stream);
+
+/* Global conservation check of a divergence field: per level k,
+ * out_sum[k] = sum_i V_i div_ik and out_abs[k] = sum_i |V_i div_ik|, both
+ * accumulated in FP64 in a fixed order (two-pass tree), so results are
+ * bitwise reproducible.  div: scalar [V][nlev] of dtype; out_sum, out_abs:
+ * device FP64 arrays [nlev].  The first call on a mesh for a given nlev may
+ * allocate an internal partial-sum buffer (kept until atlas_mesh_free). */
+int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                             const void* div, double* out_sum, double* out_abs,
+                             void* stream);
+
+/* ---- batched multi-tracer launch ------------------------------------------
+ * Many fields with different level counts go through one persistent kernel
+ * launch per operator.  Per tracer, the same arithmetic per output element
+ * as the single-field calls, so results are bitwise identical to them. */
+
+enum {
+  ATLAS_OP_GRADIENT = 1,
+  ATLAS_OP_DIVERGENCE = 2,
+  ATLAS_OP_GRADIENT_ADJOINT = 4,
+  ATLAS_OP_DIVERGENCE_ADJOINT = 8,
+  ATLAS_OP_LAPLACIAN = 16   /* tuning and launch shapes only; not batchable */
+};
+
+typedef struct {
+  int32_t nlev;          /* levels of this tracer, >= 1                    */
+  int32_t reserved;      /* must be 0                                       */
+  const void* in[4];     /* per operator bit (gradient, divergence, grad
+                            adjoint, div adjoint): input field, device      */
+  void* out[4];          /* per operator bit: output field, device          */
+} atlas_tracer_desc_t;
+
+/* Launch shape.  Zero fields mean "library default". */
+typedef struct {
+  int32_t waves_per_block;  /* 1, 2, 4, 8 or 16                             */
+  int32_t nodes_per_wave;   /* consecutive nodes a wave handles per item     */
+  int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CU count     */
+  int32_t xcd_remap;        /* 1: give each XCD a contiguous slice of work    */
+} atlas_tune_t;
+
+typedef struct atlas_batch_s* atlas_batch_t;
+
+/* Create a plan: validates descriptors (host array of ntracers entries,
+ * copied), uploads a device work table, and fixes the launch shape (tune may
+ * be NULL).  op_mask is an OR of ATLAS_OP_* bits; every tracer must give
+ * in/out pointers for every selected operator.  dtype: ATLAS_F32 or
+ * ATLAS_F64.  The plan owns its device table until atlas_batch_free. */
+int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* descs,
+                       int32_t ntracers, uint32_t op_mask, const atlas_tune_t* tune,
+                       atlas_batch_t* out);
+
+/* Enqueue one persistent launch per selected operator (in the order of the
+ * bits above) on `stream`.  Allocates nothing and never synchronises, so it
+ * may be recorded into a HIP graph by stream capture. */
+int atlas_batch_run(atlas_batch_t plan, void* stream);
+
+/* Run the plan through a HIP graph owned by the plan: the first call
+ * captures atlas_batch_run on `stream` and instantiates the graph, every
+ * call launches it on `stream`. */
+int atlas_batch_graph_launch(atlas_batch_t plan, void* stream);
+
+void atlas_batch_free(atlas_batch_t plan);
+
+/* Time candidate launch shapes of a plan (`reps` runs each after one warm-up,
+ * HIP events on `stream`, which it synchronises; the plan's fields are read
+ * and overwritten).  Re-uploads the plan's work table for each candidate,
+ * keeps the fastest shape in the plan, drops any captured graph, and writes
+ * the shape to *best and its mean time per run in milliseconds to *best_ms. */
+int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_t* best,
+                     float* best_ms);
+
+/* ---- autotuning ----------------------------------------------------------- */
+
+/* Time candidate launch shapes of one operator (one ATLAS_OP_* bit) on
+ * caller-provided device input/output fields of nlev levels (contents are
+ * read/overwritten), `reps` launches per candidate after one warm-up, with
+ * HIP events on `stream` (synchronises it).  Writes the fastest shape to
+ * *best and its mean time per launch in milliseconds to *best_ms. */
+int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
+                     const void* in, void* out, int32_t reps, void* stream,
+                     atlas_tune_t* best, float* best_ms);
+
+/* Set the launch shape used by the single-field calls for (op, dtype) on this
+ * mesh; NULL restores the default.  op: one ATLAS_OP_* bit. */
+int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op,
+                         const atlas_tune_t* tune);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATLAS_NABLA_H */

@@ -1,0 +1,320 @@
+"""MI355X (gfx950) median-dual Nabla operators on octahedral reduced Gaussian
+meshes.
+
+Thin Python binding of ``libatlas_nabla.so`` (C ABI in
+``include/atlas_nabla.h``).  Every step of every operator runs in the HIP
+kernels of that library; this module only marshals arguments: it turns torch
+tensors into device pointers, the current torch stream into a ``hipStream_t``
+and status codes into exceptions.  PyTorch provides device memory and streams.
+
+Workflow, after the Grid -> Mesh -> FunctionSpace -> Field sequence of the
+Atlas report (Section 2.3, Figure 2)::
+
+    mesh = Mesh("O1280", radius=6371220.0, device=0)
+    fs = NodeColumns(mesh, levels=137)
+    f = fs.create_field(torch.float32)            # [nnodes][137]
+    g = gradient(mesh, f)                         # [nnodes][137][2]
+    lap = laplacian(mesh, f)
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libatlas_nabla.so")
+
+F64, F32, BF16 = 0, 1, 2
+OP_GRADIENT, OP_DIVERGENCE, OP_GRADIENT_ADJOINT, OP_DIVERGENCE_ADJOINT, OP_LAPLACIAN = 1, 2, 4, 8, 16
+STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EHIP",
+          -4: "ATLAS_ENODEV", -5: "ATLAS_EDTYPE", -6: "ATLAS_ESHAPE"}
+
+
+class AtlasError(RuntimeError):
+    """A non-OK status from the C ABI."""
+
+    def __init__(self, code, message):
+        self.code = code
+        super().__init__(f"{STATUS.get(code, code)}: {message}")
+
+
+class TuneShape(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("nodes_per_wave", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class TracerDesc(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("in_", ctypes.c_void_p * 4), ("out", ctypes.c_void_p * 4)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_SIGS = {
+    "atlas_version": (ctypes.c_char_p, []),
+    "atlas_last_error": (ctypes.c_char_p, []),
+    "atlas_device_count": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int)]),
+    "atlas_mesh_build": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_P)]),
+    "atlas_mesh_free": (None, [_P]),
+    "atlas_mesh_sizes": (ctypes.c_int, [_P, _I64P, _I64P, _I64P, _I64P, ctypes.POINTER(_I32),
+                                        ctypes.POINTER(_I32)]),
+    "atlas_mesh_export_grid": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "atlas_mesh_export_connectivity": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "atlas_mesh_export_geometry": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "atlas_nabla_gradient": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_nabla_divergence": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_nabla_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_gradient_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_nabla_divergence_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_nabla_conservation": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_batch_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TracerDesc), _I32,
+                                          ctypes.c_uint32, ctypes.POINTER(TuneShape), ctypes.POINTER(_P)]),
+    "atlas_batch_run": (ctypes.c_int, [_P, _P]),
+    "atlas_batch_graph_launch": (ctypes.c_int, [_P, _P]),
+    "atlas_batch_free": (None, [_P]),
+    "atlas_batch_tune": (ctypes.c_int, [_P, _I32, _P, ctypes.POINTER(TuneShape),
+                                        ctypes.POINTER(ctypes.c_float)]),
+    "atlas_nabla_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, _I32, _P, _P, _I32, _P,
+                                        ctypes.POINTER(TuneShape), ctypes.POINTER(ctypes.c_float)]),
+    "atlas_nabla_set_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(TuneShape)]),
+}
+
+
+def lib():
+    """Load libatlas_nabla.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1908_07038_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise AtlasError(code, lib().atlas_last_error().decode())
+
+
+def version():
+    return lib().atlas_version().decode()
+
+
+def device_count():
+    n = ctypes.c_int(0)
+    code = lib().atlas_device_count(ctypes.byref(n))
+    return n.value if code == 0 else 0
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Mesh:
+    """Median-dual mesh of an octahedral grid "O<N>" (see atlas_mesh_build).
+
+    ``device`` is a HIP device ordinal, or -1 for a host-only mesh whose
+    connectivity and geometry can be exported but which runs no operator.
+    """
+
+    def __init__(self, grid, radius=6371220.0, device=0):
+        self.grid = grid
+        self.radius = float(radius)
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().atlas_mesh_build(grid.encode(), self.radius, self.device, ctypes.byref(h)))
+        self._h = h
+        v, e, t, p = (ctypes.c_int64() for _ in range(4))
+        ms, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().atlas_mesh_sizes(h, *(ctypes.byref(x) for x in (v, e, t, p, ms, nr))))
+        self.nnodes, self.nedges, self.ntris = v.value, e.value, t.value
+        self.npole_edges, self.max_slots, self.nrows = p.value, ms.value, nr.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().atlas_mesh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host exports (numpy) -------------------------------------------------
+    def export_grid(self):
+        V, R = self.nnodes, self.nrows
+        out = dict(row_size=np.empty(R, np.int32), row_off=np.empty(R + 1, np.int64),
+                   colat=np.empty(R, np.float64), lonlat=np.empty((V, 2), np.float64),
+                   xyz=np.empty((V, 3), np.float64))
+        _check(lib().atlas_mesh_export_grid(self._h, *(_np_ptr(out[k]) for k in
+                                                       ("row_size", "row_off", "colat", "lonlat", "xyz"))))
+        return out
+
+    def export_connectivity(self):
+        V, E, T = self.nnodes, self.nedges, self.ntris
+        out = dict(tris=np.empty((T, 3), np.int32), edges=np.empty((E, 2), np.int32),
+                   csr_off=np.empty(V + 1, np.int64), nbr=np.empty(2 * E, np.int32),
+                   eid=np.empty(2 * E, np.int32), sgn=np.empty(2 * E, np.int8),
+                   rev=np.empty(2 * E, np.int8), is_pole=np.empty(E, np.uint8))
+        keys = ("tris", "edges", "csr_off", "nbr", "eid", "sgn", "rev", "is_pole")
+        _check(lib().atlas_mesh_export_connectivity(self._h, *(_np_ptr(out[k]) for k in keys)))
+        return out
+
+    def export_geometry(self):
+        V, E = self.nnodes, self.nedges
+        out = dict(S=np.empty((E, 3)), V=np.empty(V), basis=np.empty((V, 2, 3)), C=np.empty((V, 3)))
+        _check(lib().atlas_mesh_export_geometry(self._h, *(_np_ptr(out[k]) for k in ("S", "V", "basis", "C"))))
+        return out
+
+    def coords(self):
+        """(lon, sin(lat), cos(lat)) of every node, for input generators."""
+        g = self.export_grid()
+        sl = np.cos(g["colat"])[np.repeat(np.arange(self.nrows), g["row_size"])]
+        cl = np.sin(g["colat"])[np.repeat(np.arange(self.nrows), g["row_size"])]
+        return g["lonlat"][:, 0].copy(), sl, cl
+
+
+class NodeColumns:
+    """Function space of node columns: fields [nnodes][levels](, 2)."""
+
+    def __init__(self, mesh, levels):
+        self.mesh = mesh
+        self.levels = int(levels)
+
+    def create_field(self, dtype, variables=1, fill=None):
+        import torch
+        shape = (self.mesh.nnodes, self.levels) + ((2,) if variables == 2 else ())
+        dev = torch.device("cuda", self.mesh.device)
+        t = torch.empty(shape, dtype=dtype, device=dev)
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+
+# ---- torch marshalling ------------------------------------------------------
+
+def _dtype_code(t):
+    import torch
+    codes = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype} (float64, float32, bfloat16)")
+    return codes[t.dtype]
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _field(mesh, t, comps, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    want = 3 if comps == 2 else 2
+    if t.dim() != want or t.shape[0] != mesh.nnodes or (comps == 2 and t.shape[2] != 2):
+        raise ValueError(f"{name} must have shape [nnodes][nlev]" + ("[2]" if comps == 2 else ""))
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.shape[1]
+
+
+def _apply(fn, mesh, x, in_comps, out_comps, out):
+    import torch
+    nlev = _field(mesh, x, in_comps, "input")
+    shape = (mesh.nnodes, nlev) + ((2,) if out_comps == 2 else ())
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    else:
+        _field(mesh, out, out_comps, "out")
+        if out.dtype != x.dtype or tuple(out.shape) != shape:
+            raise ValueError("out has the wrong dtype or shape")
+    _check(fn(mesh.handle, _dtype_code(x), nlev, ctypes.c_void_p(x.data_ptr()),
+              ctypes.c_void_p(out.data_ptr()), _stream(x)))
+    return out
+
+
+def gradient(mesh, f, out=None):
+    """[V][L] -> [V][L][2] (east, north)."""
+    return _apply(lib().atlas_nabla_gradient, mesh, f, 1, 2, out)
+
+
+def divergence(mesh, uv, out=None):
+    """[V][L][2] -> [V][L]."""
+    return _apply(lib().atlas_nabla_divergence, mesh, uv, 2, 1, out)
+
+
+def gradient_adjoint(mesh, w, out=None):
+    """[V][L][2] -> [V][L], exact transpose of :func:`gradient`."""
+    return _apply(lib().atlas_nabla_gradient_adjoint, mesh, w, 2, 1, out)
+
+
+def divergence_adjoint(mesh, d, out=None):
+    """[V][L] -> [V][L][2], exact transpose of :func:`divergence`."""
+    return _apply(lib().atlas_nabla_divergence_adjoint, mesh, d, 1, 2, out)
+
+
+def laplacian(mesh, f, out=None, workspace=None):
+    """div(grad f): fused two-ring pass, or two passes through ``workspace``
+    ([V][L][2], same dtype) when given."""
+    import torch
+    nlev = _field(mesh, f, 1, "f")
+    if out is None:
+        out = torch.empty_like(f)
+    ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    if workspace is not None:
+        _field(mesh, workspace, 2, "workspace")
+    _check(lib().atlas_nabla_laplacian(mesh.handle, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), ws, _stream(f)))
+    return out
+
+
+def conservation(mesh, div):
+    """Per-level FP64 (sum V_i div_ik, sum |V_i div_ik|) as device tensors."""
+    import torch
+    nlev = _field(mesh, div, 1, "div")
+    s = torch.empty(nlev, dtype=torch.float64, device=div.device)
+    a = torch.empty(nlev, dtype=torch.float64, device=div.device)
+    _check(lib().atlas_nabla_conservation(mesh.handle, _dtype_code(div), nlev, ctypes.c_void_p(div.data_ptr()),
+                                          ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(a.data_ptr()),
+                                          _stream(div)))
+    return s, a
+
+
+def tune(mesh, op, x, out, reps=10):
+    """Time launch shapes of one operator on (x, out); returns (shape dict, ms)."""
+    best = TuneShape()
+    ms = ctypes.c_float()
+    nlev = x.shape[1]
+    _check(lib().atlas_nabla_tune(mesh.handle, _dtype_code(x), op, nlev, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), reps, _stream(x), ctypes.byref(best),
+                                  ctypes.byref(ms)))
+    return best.as_dict(), ms.value
+
+
+def set_tune(mesh, op, dtype_code, shape=None):
+    """Fix the launch shape of (op, dtype) on this mesh; None restores the default."""
+    if shape is None:
+        _check(lib().atlas_nabla_set_tune(mesh.handle, dtype_code, op, None))
+    else:
+        ts = TuneShape(**shape)
+        _check(lib().atlas_nabla_set_tune(mesh.handle, dtype_code, op, ctypes.byref(ts)))
+
+
+from .autograd import Gradient, Divergence, Laplacian, grad, div, lap  # noqa: E402,F401
+from .batch import Batch  # noqa: E402,F401

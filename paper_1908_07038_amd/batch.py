@@ -1,0 +1,97 @@
+"""Batched multi-tracer plans: one persistent launch per operator over many
+fields with different level counts, optionally replayed as a HIP graph."""
+
+import ctypes
+
+from . import (F32, F64, OP_DIVERGENCE, OP_DIVERGENCE_ADJOINT, OP_GRADIENT, OP_GRADIENT_ADJOINT,
+               TracerDesc, TuneShape, _check, _dtype_code, _stream, lib)
+
+_OPS = {"gradient": OP_GRADIENT, "divergence": OP_DIVERGENCE,
+        "gradient_adjoint": OP_GRADIENT_ADJOINT, "divergence_adjoint": OP_DIVERGENCE_ADJOINT}
+_BIT = {OP_GRADIENT: 0, OP_DIVERGENCE: 1, OP_GRADIENT_ADJOINT: 2, OP_DIVERGENCE_ADJOINT: 3}
+_COMPS = {OP_GRADIENT: (1, 2), OP_DIVERGENCE: (2, 1), OP_GRADIENT_ADJOINT: (2, 1),
+          OP_DIVERGENCE_ADJOINT: (1, 2)}
+
+
+class Batch:
+    """Plan over ``tracers``: a list of dicts {op name: (input, output)}.
+
+    Every tracer must give tensors for the same set of operators.  The plan
+    keeps references to the tensors; their storage must stay alive and in
+    place while the plan is used.
+    """
+
+    def __init__(self, mesh, tracers, tune=None):
+        if not tracers:
+            raise ValueError("need at least one tracer")
+        names = set(tracers[0])
+        if not names or not names <= set(_OPS):
+            raise ValueError(f"operators must be among {sorted(_OPS)}")
+        mask = 0
+        for n in names:
+            mask |= _OPS[n]
+        self.mesh = mesh
+        self.mask = mask
+        self._keep = []
+        descs = (TracerDesc * len(tracers))()
+        dtype = None
+        for t, tr in enumerate(tracers):
+            if set(tr) != names:
+                raise ValueError("all tracers must use the same operators")
+            nlev = None
+            for n, (x, y) in tr.items():
+                op = _OPS[n]
+                ci, co = _COMPS[op]
+                if x.shape[0] != mesh.nnodes or y.shape[0] != mesh.nnodes:
+                    raise ValueError("fields must be [nnodes][nlev](, 2)")
+                if (x.dim() != (3 if ci == 2 else 2)) or (y.dim() != (3 if co == 2 else 2)):
+                    raise ValueError(f"tracer {t} {n}: wrong field rank")
+                if not (x.is_contiguous() and y.is_contiguous()) or x.dtype != y.dtype:
+                    raise ValueError(f"tracer {t} {n}: fields must be contiguous and of one dtype")
+                if nlev is None:
+                    nlev = x.shape[1]
+                if x.shape[1] != nlev or y.shape[1] != nlev:
+                    raise ValueError(f"tracer {t}: all fields need the same level count")
+                dtype = _dtype_code(x) if dtype is None else dtype
+                if _dtype_code(x) != dtype:
+                    raise ValueError("one dtype per plan")
+                b = _BIT[op]
+                descs[t].in_[b] = x.data_ptr()
+                descs[t].out[b] = y.data_ptr()
+                self._keep += [x, y]
+            descs[t].nlev = nlev
+        if dtype not in (F32, F64):
+            raise ValueError("batched plans take float32 or float64 fields")
+        self.dtype = dtype
+        self.device_tensor = tracers[0][next(iter(names))][0]
+        ts = TuneShape(**tune) if tune else None
+        h = ctypes.c_void_p()
+        _check(lib().atlas_batch_create(mesh.handle, dtype, descs, len(tracers), mask,
+                                        ctypes.byref(ts) if ts is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        """Enqueue one persistent launch per operator on the current stream."""
+        _check(lib().atlas_batch_run(self._h, _stream(self.device_tensor)))
+
+    def graph_launch(self):
+        """Replay the plan as a HIP graph on the current stream (captured once)."""
+        _check(lib().atlas_batch_graph_launch(self._h, _stream(self.device_tensor)))
+
+    def tune(self, reps=3):
+        best = TuneShape()
+        ms = ctypes.c_float()
+        _check(lib().atlas_batch_tune(self._h, reps, _stream(self.device_tensor), ctypes.byref(best),
+                                      ctypes.byref(ms)))
+        return best.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().atlas_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,695 @@
+// C ABI of the Nabla library (declared in include/atlas_nabla.h): argument
+// checking, mesh ownership, device upload of the operator tables, and
+// dispatch to the gfx950 kernels.  No C++ exception crosses this layer.
+#include "atlas_nabla.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "mesh.hpp"
+
+using namespace atlasnabla;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(ATLAS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Current-device guard: operator calls run on the mesh's device and leave the
+// caller's current device unchanged.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+size_t dtype_size(int dtype) {
+  switch (dtype) {
+    case ATLAS_F64: return 8;
+    case ATLAS_F32: return 4;
+    case ATLAS_BF16: return 2;
+    default: return 0;
+  }
+}
+
+}  // namespace
+
+struct atlas_mesh_s {
+  HostMesh host;
+  int device = -1;
+  int num_cus = 0;
+  std::vector<void*> allocations;
+  DevTables tab64, tab32;
+  double* vol = nullptr;
+  std::mutex scratch_mu;
+  double* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  Shape shape[OP_COUNT][3];
+
+  ~atlas_mesh_s() {
+    if (device >= 0) {
+      DeviceGuard g(device);
+      for (void* p : allocations) (void)hipFree(p);
+      if (scratch) (void)hipFree(scratch);
+    }
+  }
+
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    void* p = nullptr;
+    const size_t bytes = v.size() * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e != hipSuccess) throw std::bad_alloc();
+    allocations.push_back(p);
+    if (bytes) {
+      e = hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) throw std::runtime_error(std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    return static_cast<T*>(p);
+  }
+
+  const DevTables& tables(int dtype) const { return dtype == ATLAS_F64 ? tab64 : tab32; }
+};
+
+namespace {
+
+std::vector<float> to_f32(const std::vector<double>& v) {
+  std::vector<float> r(v.size());
+  for (size_t i = 0; i < v.size(); ++i) r[i] = (float)v[i];
+  return r;
+}
+
+void upload_tables(atlas_mesh_s& m) {
+  OpTables t;
+  build_op_tables(m.host, t);
+  const int32_t* nbr8 = m.upload(t.nbr8);
+  const int32_t* lap_nbr = m.upload(t.lap_nbr);
+  m.tab64.nbr8 = m.tab32.nbr8 = nbr8;
+  m.tab64.lap_nbr = m.tab32.lap_nbr = lap_nbr;
+  m.tab64.lap_stride = m.tab32.lap_stride = t.lap_stride;
+  const std::vector<double>* src[4] = {&t.grad, &t.div, &t.gradT, &t.divT};
+  for (int o = 0; o < 4; ++o) {
+    m.tab64.coef[o] = m.upload(*src[o]);
+    m.tab32.coef[o] = m.upload(to_f32(*src[o]));
+  }
+  m.tab64.lap_w = m.upload(t.lap_w);
+  m.tab32.lap_w = m.upload(to_f32(t.lap_w));
+  m.vol = m.upload(m.host.vol);
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+int op_from_bit(uint32_t bit) {
+  switch (bit) {
+    case ATLAS_OP_GRADIENT: return OP_GRAD;
+    case ATLAS_OP_DIVERGENCE: return OP_DIV;
+    case ATLAS_OP_GRADIENT_ADJOINT: return OP_GRADT;
+    case ATLAS_OP_DIVERGENCE_ADJOINT: return OP_DIVT;
+    case ATLAS_OP_LAPLACIAN: return OP_LAP;
+    default: return -1;
+  }
+}
+
+// components of the input and output fields of each operator
+const int kInComps[OP_COUNT] = {1, 2, 2, 1, 1};
+const int kOutComps[OP_COUNT] = {2, 1, 1, 2, 1};
+const char* kOpName[OP_COUNT] = {"gradient", "divergence", "gradient_adjoint", "divergence_adjoint", "laplacian"};
+
+int check_mesh_device(atlas_mesh_t mesh) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  if (mesh->device < 0) return fail(ATLAS_ENODEV, "mesh was built host-only (device = -1)");
+  return ATLAS_OK;
+}
+
+int check_field(const void* p, size_t comps, size_t esize, const char* name) {
+  if (!p) return fail(ATLAS_EINVAL, std::string(name) + " is NULL");
+  if ((uintptr_t)p % (comps * esize) != 0)
+    return fail(ATLAS_EINVAL, std::string(name) + " is not aligned to " + std::to_string(comps * esize) + " bytes");
+  return ATLAS_OK;
+}
+
+int check_shape(Shape& s, const atlas_tune_t* t) {
+  if (!t) return ATLAS_OK;
+  if (t->waves_per_block) {
+    const int w = t->waves_per_block;
+    if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16) return fail(ATLAS_EINVAL, "waves_per_block must be 1,2,4,8,16");
+    s.waves_per_block = w;
+  }
+  if (t->nodes_per_wave) {
+    if (t->nodes_per_wave < 1 || t->nodes_per_wave > 64) return fail(ATLAS_EINVAL, "nodes_per_wave must be 1..64");
+    s.nodes_per_wave = t->nodes_per_wave;
+  }
+  if (t->blocks_per_cu) {
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(ATLAS_EINVAL, "blocks_per_cu must be 1..64");
+    s.blocks_per_cu = t->blocks_per_cu;
+  }
+  if (t->xcd_remap < 0 || t->xcd_remap > 1) return fail(ATLAS_EINVAL, "xcd_remap must be 0 or 1");
+  s.xcd_remap = t->xcd_remap;
+  return ATLAS_OK;
+}
+
+int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, void* out, void* stream,
+           const Shape* shape_override = nullptr) {
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  const int64_t V = mesh->host.V;
+  if ((int64_t)nlev > (int64_t)INT32_MAX / 2) return fail(ATLAS_ESHAPE, "nlev too large");
+  if ((rc = check_field(in, kInComps[op], es, "input"))) return rc;
+  if ((rc = check_field(out, kOutComps[op], es, "output"))) return rc;
+  const size_t nin = (size_t)V * nlev * kInComps[op] * es;
+  const size_t nout = (size_t)V * nlev * kOutComps[op] * es;
+  if (overlaps(in, nin, out, nout)) return fail(ATLAS_EINVAL, "output overlaps input");
+  DeviceGuard g(mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  const Shape& sh = shape_override ? *shape_override : mesh->shape[op][dtype];
+  hipError_t e = launch_op(op, dtype, mesh->tables(dtype), V, nlev, in, out, sh, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, kOpName[op]);
+  return ATLAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* atlas_version(void) { return "atlas-nabla 0.1.0 gfx950"; }
+
+const char* atlas_last_error(void) { return g_err.c_str(); }
+
+int atlas_device_count(int* count) {
+  if (!count) return fail(ATLAS_EINVAL, "count is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    *count = 0;
+    return fail(ATLAS_ENODEV, "no HIP device available");
+  }
+  *count = n;
+  return ATLAS_OK;
+}
+
+int atlas_mesh_build(const char* grid, double radius, int device, atlas_mesh_t* out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid) return fail(ATLAS_EINVAL, "grid name is NULL");
+  const int N = parse_grid_name(grid);
+  if (N < 1) return fail(ATLAS_EINVAL, std::string("not an octahedral grid name: '") + grid + "'");
+  if (!(radius > 0.0) || radius > 1e300) return fail(ATLAS_EINVAL, "radius must be positive and finite");
+  if (device < -1) return fail(ATLAS_ENODEV, "bad device ordinal");
+  int ndev = 0;
+  if (device >= 0) {
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+      (void)hipGetLastError();
+      return fail(ATLAS_ENODEV, "no HIP device available");
+    }
+    if (device >= ndev) return fail(ATLAS_ENODEV, "device ordinal out of range");
+  }
+  atlas_mesh_s* m = nullptr;
+  try {
+    m = new atlas_mesh_s();
+    build_host_mesh(N, radius, m->host);
+    if (device >= 0) {
+      DeviceGuard g(device);
+      if (!g.ok) {
+        delete m;
+        return fail(ATLAS_EHIP, "cannot select device");
+      }
+      m->device = device;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->num_cus = prop.multiProcessorCount;
+      if (m->num_cus <= 0) m->num_cus = 256;
+      upload_tables(*m);
+    }
+  } catch (const std::bad_alloc&) {
+    delete m;
+    return fail(ATLAS_ENOMEM, "out of memory building mesh " + std::string(grid));
+  } catch (const std::length_error& e) {
+    delete m;
+    return fail(ATLAS_ESHAPE, e.what());
+  } catch (const std::exception& e) {
+    delete m;
+    return fail(ATLAS_EHIP, e.what());
+  }
+  *out = m;
+  return ATLAS_OK;
+}
+
+void atlas_mesh_free(atlas_mesh_t mesh) { delete mesh; }
+
+int atlas_mesh_sizes(atlas_mesh_t mesh, int64_t* nnodes, int64_t* nedges, int64_t* ntris, int64_t* npole_edges,
+                     int32_t* max_slots, int32_t* nrows) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  const HostMesh& h = mesh->host;
+  if (nnodes) *nnodes = h.V;
+  if (nedges) *nedges = h.E;
+  if (ntris) *ntris = h.T;
+  if (npole_edges) *npole_edges = h.npole;
+  if (max_slots) *max_slots = h.max_degree;
+  if (nrows) *nrows = h.nrows;
+  return ATLAS_OK;
+}
+
+int atlas_mesh_export_grid(atlas_mesh_t mesh, int32_t* row_size, int64_t* row_off, double* colat, double* lonlat,
+                           double* xyz) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  const HostMesh& h = mesh->host;
+  if (row_size) std::memcpy(row_size, h.row_size.data(), h.row_size.size() * sizeof(int32_t));
+  if (row_off) std::memcpy(row_off, h.row_off.data(), h.row_off.size() * sizeof(int64_t));
+  if (colat) std::memcpy(colat, h.colat.data(), h.colat.size() * sizeof(double));
+  if (lonlat)
+    for (int64_t i = 0; i < h.V; ++i) {
+      lonlat[2 * i] = h.lon[i];
+      lonlat[2 * i + 1] = 0.5 * M_PI - h.colat[h.node_row[i]];
+    }
+  if (xyz) std::memcpy(xyz, h.xyz.data(), h.xyz.size() * sizeof(double));
+  return ATLAS_OK;
+}
+
+int atlas_mesh_export_connectivity(atlas_mesh_t mesh, int32_t* tris, int32_t* edges, int64_t* csr_off, int32_t* nbr,
+                                   int32_t* eid, int8_t* sgn, int8_t* rev, uint8_t* is_pole) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  const HostMesh& h = mesh->host;
+  if (tris) std::memcpy(tris, h.tris.data(), h.tris.size() * sizeof(int32_t));
+  if (edges) std::memcpy(edges, h.edges.data(), h.edges.size() * sizeof(int32_t));
+  if (csr_off) std::memcpy(csr_off, h.csr_off.data(), h.csr_off.size() * sizeof(int64_t));
+  if (nbr) std::memcpy(nbr, h.nbr.data(), h.nbr.size() * sizeof(int32_t));
+  if (eid) std::memcpy(eid, h.eid.data(), h.eid.size() * sizeof(int32_t));
+  if (sgn) std::memcpy(sgn, h.sgn.data(), h.sgn.size() * sizeof(int8_t));
+  if (rev) std::memcpy(rev, h.rev.data(), h.rev.size() * sizeof(int8_t));
+  if (is_pole) std::memcpy(is_pole, h.is_pole.data(), h.is_pole.size() * sizeof(uint8_t));
+  return ATLAS_OK;
+}
+
+int atlas_mesh_export_geometry(atlas_mesh_t mesh, double* S, double* V, double* basis, double* C) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  const HostMesh& h = mesh->host;
+  if (S) std::memcpy(S, h.S.data(), h.S.size() * sizeof(double));
+  if (V) std::memcpy(V, h.vol.data(), h.vol.size() * sizeof(double));
+  if (basis) std::memcpy(basis, h.basis.data(), h.basis.size() * sizeof(double));
+  if (C) std::memcpy(C, h.C.data(), h.C.size() * sizeof(double));
+  return ATLAS_OK;
+}
+
+int atlas_nabla_gradient(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* f, void* grad, void* stream) {
+  return run_op(mesh, OP_GRAD, dtype, nlev, f, grad, stream);
+}
+
+int atlas_nabla_divergence(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* div, void* stream) {
+  return run_op(mesh, OP_DIV, dtype, nlev, uv, div, stream);
+}
+
+int atlas_nabla_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* w, void* fbar,
+                                 void* stream) {
+  return run_op(mesh, OP_GRADT, dtype, nlev, w, fbar, stream);
+}
+
+int atlas_nabla_divergence_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* d, void* uvbar,
+                                   void* stream) {
+  return run_op(mesh, OP_DIVT, dtype, nlev, d, uvbar, stream);
+}
+
+int atlas_nabla_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* f, void* lap, void* workspace,
+                          void* stream) {
+  if (!workspace) return run_op(mesh, OP_LAP, dtype, nlev, f, lap, stream);
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  const size_t n1 = (size_t)mesh->host.V * nlev * es;
+  if ((rc = check_field(workspace, 2, es, "workspace"))) return rc;
+  if (f && overlaps(workspace, 2 * n1, f, n1)) return fail(ATLAS_EINVAL, "workspace overlaps input");
+  if (lap && overlaps(workspace, 2 * n1, lap, n1)) return fail(ATLAS_EINVAL, "workspace overlaps output");
+  if (f && lap && overlaps(f, n1, lap, n1)) return fail(ATLAS_EINVAL, "output overlaps input");
+  if ((rc = run_op(mesh, OP_GRAD, dtype, nlev, f, workspace, stream))) return rc;
+  return run_op(mesh, OP_DIV, dtype, nlev, workspace, lap, stream);
+}
+
+int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* div, double* out_sum,
+                             double* out_abs, void* stream) {
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  if ((rc = check_field(div, 1, es, "div"))) return rc;
+  if ((rc = check_field(out_sum, 1, 8, "out_sum"))) return rc;
+  if ((rc = check_field(out_abs, 1, 8, "out_abs"))) return rc;
+  if (overlaps(out_sum, 8 * (size_t)nlev, out_abs, 8 * (size_t)nlev))
+    return fail(ATLAS_EINVAL, "out_sum overlaps out_abs");
+  DeviceGuard g(mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  const int64_t V = mesh->host.V;
+  const size_t need = (size_t)conservation_parts(V, nlev) * nlev * 2 * sizeof(double);
+  double* scratch = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mesh->scratch_mu);
+    if (mesh->scratch_bytes < need) {
+      if (mesh->scratch) {
+        // a previous call may still be using the smaller buffer
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "conservation");
+        (void)hipFree(mesh->scratch);
+        mesh->scratch = nullptr;
+        mesh->scratch_bytes = 0;
+      }
+      void* p = nullptr;
+      if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ATLAS_ENOMEM, "cannot allocate conservation partials");
+      }
+      mesh->scratch = static_cast<double*>(p);
+      mesh->scratch_bytes = need;
+    }
+    scratch = mesh->scratch;
+  }
+  hipError_t e = launch_conservation(dtype, mesh->vol, V, nlev, div, scratch, out_sum, out_abs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "conservation");
+  return ATLAS_OK;
+}
+
+int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op, const atlas_tune_t* tune) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  if (!dtype_size(dtype)) return fail(ATLAS_EDTYPE, "unknown dtype");
+  const int o = op_from_bit(op);
+  if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit");
+  Shape s;
+  int rc = check_shape(s, tune);
+  if (rc) return rc;
+  mesh->shape[o][dtype] = s;
+  return ATLAS_OK;
+}
+
+int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, const void* in, void* out, int32_t reps,
+                     void* stream, atlas_tune_t* best, float* best_ms) {
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const int o = op_from_bit(op);
+  if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit");
+  if (reps < 1 || reps > 10000) return fail(ATLAS_EINVAL, "reps must be 1..10000");
+  if (!best) return fail(ATLAS_EINVAL, "best is NULL");
+  // argument check through a normal call with the default shape
+  if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream))) return rc;
+  DeviceGuard g(mesh->device);
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(ATLAS_EHIP, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ATLAS_EHIP, "hipEventCreate");
+  }
+  float bestt = 1e30f;
+  Shape bs = mesh->shape[o][dtype];
+  const int wpbs[] = {1, 2, 4, 8};
+  const int npws[] = {1, 2, 4, 8};
+  for (int w : wpbs)
+    for (int n : npws)
+      for (int x = 0; x < 2; ++x) {
+        Shape s;
+        s.waves_per_block = w;
+        s.nodes_per_wave = n;
+        s.xcd_remap = x;
+        if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream, &s))) goto done;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r)
+          if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream, &s))) goto done;
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(ATLAS_EHIP, "hipEventSynchronize");
+          goto done;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms < bestt) {
+          bestt = ms;
+          bs = s;
+        }
+      }
+  best->waves_per_block = bs.waves_per_block;
+  best->nodes_per_wave = bs.nodes_per_wave;
+  best->blocks_per_cu = bs.blocks_per_cu;
+  best->xcd_remap = bs.xcd_remap;
+  if (best_ms) *best_ms = bestt;
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // extern "C"
+
+// ---- batched plans ------------------------------------------------------------
+
+struct atlas_batch_s {
+  atlas_mesh_t mesh = nullptr;
+  int dtype = 0;
+  uint32_t mask = 0;
+  Shape shape;
+  std::vector<atlas_tracer_desc_t> descs;
+  BatchItem* items[4] = {};
+  int64_t total[4] = {};
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  void release_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~atlas_batch_s() {
+    if (!mesh) return;
+    DeviceGuard g(mesh->device);
+    release_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (auto* p : items)
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+// (Re)build the device work tables of a plan for its current shape.
+int plan_upload(atlas_batch_s* b) {
+  const int64_t V = b->mesh->host.V;
+  for (int o = 0; o < 4; ++o) {
+    if (b->items[o]) {
+      (void)hipFree(b->items[o]);
+      b->items[o] = nullptr;
+    }
+    if (!(b->mask & (1u << o))) continue;
+    std::vector<BatchItem> host(b->descs.size());
+    int64_t tile = 0;
+    for (size_t t = 0; t < b->descs.size(); ++t) {
+      const int L = b->descs[t].nlev;
+      host[t].in = b->descs[t].in[o];
+      host[t].out = b->descs[t].out[o];
+      host[t].nlev = L;
+      host[t].pack = pack_factor(L);
+      host[t].tile_begin = tile;
+      tile += tiles_for(V, L, b->shape);
+    }
+    b->total[o] = tile;
+    void* p = nullptr;
+    if (hipMalloc(&p, host.size() * sizeof(BatchItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ATLAS_ENOMEM, "cannot allocate batch table");
+    }
+    b->items[o] = static_cast<BatchItem*>(p);
+    hipError_t e = hipMemcpy(p, host.data(), host.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch table upload");
+  }
+  return ATLAS_OK;
+}
+
+int plan_run(atlas_batch_s* b, hipStream_t st, const Shape& sh) {
+  const int64_t V = b->mesh->host.V;
+  for (int o = 0; o < 4; ++o) {
+    if (!(b->mask & (1u << o))) continue;
+    hipError_t e = launch_batched(o, b->dtype, b->mesh->tables(b->dtype), V, b->items[o], (int)b->descs.size(),
+                                  b->total[o], sh, b->mesh->num_cus, st);
+    if (e != hipSuccess) return hip_fail(e, kOpName[o]);
+  }
+  return ATLAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* descs, int32_t ntracers,
+                       uint32_t op_mask, const atlas_tune_t* tune, atlas_batch_t* out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  if (dtype != ATLAS_F32 && dtype != ATLAS_F64) return fail(ATLAS_EDTYPE, "batched plans take ATLAS_F32 or ATLAS_F64");
+  if (!descs || ntracers < 1) return fail(ATLAS_EINVAL, "need at least one tracer descriptor");
+  if (op_mask == 0 || (op_mask & ~0xFu)) return fail(ATLAS_EINVAL, "op_mask must be a non-empty OR of the four operator bits");
+  const size_t es = dtype_size(dtype);
+  for (int32_t t = 0; t < ntracers; ++t) {
+    const atlas_tracer_desc_t& d = descs[t];
+    if (d.nlev < 1 || d.reserved != 0)
+      return fail(ATLAS_ESHAPE, "tracer " + std::to_string(t) + ": nlev must be >= 1 and reserved 0");
+    for (int o = 0; o < 4; ++o) {
+      if (!(op_mask & (1u << o))) continue;
+      const std::string nm = "tracer " + std::to_string(t) + " " + kOpName[o];
+      if ((rc = check_field(d.in[o], kInComps[o], es, (nm + " input").c_str()))) return rc;
+      if ((rc = check_field(d.out[o], kOutComps[o], es, (nm + " output").c_str()))) return rc;
+      const size_t n = (size_t)mesh->host.V * d.nlev * es;
+      if (overlaps(d.in[o], n * kInComps[o], d.out[o], n * kOutComps[o]))
+        return fail(ATLAS_EINVAL, nm + ": output overlaps input");
+    }
+  }
+  atlas_batch_s* b = nullptr;
+  try {
+    b = new atlas_batch_s();
+  } catch (const std::bad_alloc&) {
+    return fail(ATLAS_ENOMEM, "out of memory");
+  }
+  b->mesh = mesh;
+  b->dtype = dtype;
+  b->mask = op_mask;
+  if ((rc = check_shape(b->shape, tune))) {
+    delete b;
+    return rc;
+  }
+  b->descs.assign(descs, descs + ntracers);
+  DeviceGuard g(mesh->device);
+  if ((rc = plan_upload(b))) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return ATLAS_OK;
+}
+
+int atlas_batch_run(atlas_batch_t plan, void* stream) {
+  if (!plan) return fail(ATLAS_EINVAL, "plan is NULL");
+  DeviceGuard g(plan->mesh->device);
+  return plan_run(plan, (hipStream_t)stream, plan->shape);
+}
+
+int atlas_batch_graph_launch(atlas_batch_t plan, void* stream) {
+  if (!plan) return fail(ATLAS_EINVAL, "plan is NULL");
+  DeviceGuard g(plan->mesh->device);
+  if (!plan->exec) {
+    hipError_t e;
+    if (!plan->capture_stream) {
+      e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = plan_run(plan, plan->capture_stream, plan->shape);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(plan->capture_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    plan->graph = graph;
+    e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      plan->release_graph();
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ATLAS_OK;
+}
+
+void atlas_batch_free(atlas_batch_t plan) { delete plan; }
+
+int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_t* best, float* best_ms) {
+  if (!plan) return fail(ATLAS_EINVAL, "plan is NULL");
+  if (reps < 1 || reps > 10000) return fail(ATLAS_EINVAL, "reps must be 1..10000");
+  if (!best) return fail(ATLAS_EINVAL, "best is NULL");
+  DeviceGuard g(plan->mesh->device);
+  hipStream_t st = (hipStream_t)stream;
+  plan->release_graph();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(ATLAS_EHIP, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ATLAS_EHIP, "hipEventCreate");
+  }
+  const Shape orig = plan->shape;
+  Shape bs = orig;
+  float bestt = 1e30f;
+  int rc = ATLAS_OK;
+  const int wpbs[] = {2, 4, 8};
+  const int npws[] = {1, 2, 4};
+  const int bpcs[] = {2, 4, 8};
+  for (int w : wpbs)
+    for (int n : npws)
+      for (int c : bpcs)
+        for (int x = 0; x < 2; ++x) {
+          Shape s;
+          s.waves_per_block = w;
+          s.nodes_per_wave = n;
+          s.blocks_per_cu = c;
+          s.xcd_remap = x;
+          plan->shape = s;
+          if (hipStreamSynchronize(st) != hipSuccess) { rc = fail(ATLAS_EHIP, "hipStreamSynchronize"); goto done; }
+          if ((rc = plan_upload(plan))) goto done;
+          if ((rc = plan_run(plan, st, s))) goto done;
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < reps; ++r)
+            if ((rc = plan_run(plan, st, s))) goto done;
+          (void)hipEventRecord(e1, st);
+          if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ATLAS_EHIP, "hipEventSynchronize"); goto done; }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          ms /= (float)reps;
+          if (ms < bestt) { bestt = ms; bs = s; }
+        }
+  best->waves_per_block = bs.waves_per_block;
+  best->nodes_per_wave = bs.nodes_per_wave;
+  best->blocks_per_cu = bs.blocks_per_cu;
+  best->xcd_remap = bs.xcd_remap;
+  if (best_ms) *best_ms = bestt;
+done:
+  // leave the plan with the best shape found (or its original one on error)
+  plan->shape = rc ? orig : bs;
+  (void)hipStreamSynchronize(st);
+  int rc2 = plan_upload(plan);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc ? rc : rc2;
+}
+
+}  // extern "C"

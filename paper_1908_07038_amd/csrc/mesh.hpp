@@ -1,0 +1,78 @@
+// Host-side mesh of an octahedral reduced Gaussian grid with its median dual
+// and the per-node operator tables the gfx950 kernels read.
+//
+// The Atlas report describes Grid -> Mesh -> FunctionSpace -> Field
+// (Section 2.3, Figure 2) and leaves grid and mesh generation to other
+// documents; the definitions implemented here are stated in
+// include/atlas_nabla.h (atlas_mesh_build) and in mesh_build.cpp.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace atlasnabla {
+
+constexpr int kCapPoints = 20;   // points of each polar row
+constexpr int kEll = 8;          // slots per node record: 7 neighbours + 1 header
+constexpr int kLapStride = 24;   // two-ring record: up to 23 entries + the count
+
+struct HostMesh {
+  int N = 0;
+  double radius = 0.0;
+  int nrows = 0;
+  int64_t V = 0, E = 0, T = 0;
+
+  std::vector<int32_t> row_size;   // [nrows]
+  std::vector<int64_t> row_off;    // [nrows+1]
+  std::vector<double> colat;       // [nrows]
+  std::vector<int32_t> node_row;   // [V]
+  std::vector<double> lon, coslon, sinlon, sinlat, coslat;  // [V]
+  std::vector<double> xyz;         // [V][3]
+
+  std::vector<int32_t> tris;       // [T][3]
+  std::vector<int32_t> edges;      // [E][2]
+  std::vector<int32_t> tri_edge;   // [T][3], side s = (t_s, t_s+1)
+  std::vector<int32_t> edge_tris;  // [E][2], ascending
+  std::vector<int64_t> csr_off;    // [V+1]
+  std::vector<int32_t> nbr, eid;   // [2E]
+  std::vector<int8_t> sgn, rev;    // [2E]
+  std::vector<uint8_t> is_pole;    // [E]
+  int64_t npole = 0;
+  int max_degree = 0;
+
+  std::vector<double> S;           // [E][3] dual normals (m)
+  std::vector<double> vol;         // [V] dual areas (m^2)
+  std::vector<double> basis;       // [V][2][3] east, north
+  std::vector<double> C;           // [V][3] closure
+};
+
+// Per-node operator tables in FP64, later rounded to FP32 for the FP32 and
+// BF16 kernels.  Record layout per node (kEll slots):
+//   nbr8[i][s]   neighbour of slot s (s < deg), i itself for s >= deg,
+//   nbr8[i][7]   deg
+//   coef[i][s]   (x, y) coefficient pair of slot s, (0, 0) padding,
+//   coef[i][7]   the diagonal pair of the operator.
+struct OpTables {
+  std::vector<int32_t> nbr8;        // [V][8]
+  std::vector<double> grad;         // [V][8][2]  (a, b); diag (A, B)
+  std::vector<double> div;          // [V][8][2]  (c, d); diag (A, B)
+  std::vector<double> gradT;        // [V][8][2]  (a, b) of the reverse slot; diag (-A, -B)
+  std::vector<double> divT;         // [V][8][2]  (c, d) of the reverse slot; diag (A, B)
+  int lap_stride = kLapStride;      // entries per node in the two-ring table
+  std::vector<int32_t> lap_nbr;     // [V][lap_stride]: neighbours, then padding (i);
+                                    // entry lap_stride-1 holds the count
+  std::vector<double> lap_w;        // [V][lap_stride]
+};
+
+// Parse "O<N>"; returns N or -1.
+int parse_grid_name(const std::string& name);
+
+// Build grid, connectivity and dual geometry.  Throws std::runtime_error /
+// std::bad_alloc on failure.
+void build_host_mesh(int N, double radius, HostMesh& m);
+
+// Build the per-node tables from the geometry.
+void build_op_tables(const HostMesh& m, OpTables& t);
+
+}  // namespace atlasnabla

@@ -1,0 +1,111 @@
+"""C ABI checks that need no GPU: every declared symbol is exported, the host
+mesh builder matches the oracle bit for bit on connectivity and positions and
+to rounding on geometry, and argument errors come back as status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1908_07038_amd as pa
+from _oracle_cache import mesh_and_dual
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(atlas_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 20, names
+    L = ctypes.CDLL(pa.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding declares a signature for each
+    assert set(names) <= set(pa._SIGS), set(names) - set(pa._SIGS)
+
+
+def test_version():
+    assert pa.version().startswith("atlas-nabla")
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 32, 128])
+def test_host_mesh_matches_oracle(N):
+    M = pa.Mesh(f"O{N}", device=-1)
+    m, g = mesh_and_dual(N)
+    assert (M.nnodes, M.nedges, M.ntris, M.npole_edges) == (m.nnodes, m.nedges, m.ntris, 34)
+    assert M.max_slots == m.degree.max()
+    c = M.export_connectivity()
+    np.testing.assert_array_equal(c["tris"], m.tris)
+    np.testing.assert_array_equal(c["edges"], m.edges)
+    np.testing.assert_array_equal(c["csr_off"], m.off)
+    np.testing.assert_array_equal(c["nbr"], m.nbr)
+    np.testing.assert_array_equal(c["eid"], m.eid)
+    np.testing.assert_array_equal(c["sgn"], m.sgn)
+    np.testing.assert_array_equal(c["rev"], m.rev)
+    np.testing.assert_array_equal(c["is_pole"].astype(bool), m.is_pole)
+    gr = M.export_grid()
+    np.testing.assert_array_equal(gr["row_size"], m.grid.row_size)
+    np.testing.assert_array_equal(gr["row_off"], m.grid.row_off)
+    # positions: bit for bit (they enter every dual quantity through differences)
+    np.testing.assert_array_equal(gr["colat"], m.grid.theta)
+    np.testing.assert_array_equal(gr["xyz"], m.grid.xyz)
+    np.testing.assert_array_equal(gr["lonlat"][:, 0], m.grid.lon)
+    ge = M.export_geometry()
+    rel = np.linalg.norm(ge["S"] - g.S, axis=1) / np.linalg.norm(g.S, axis=1)
+    assert rel.max() < 2e-15
+    np.testing.assert_allclose(ge["V"], g.V, rtol=2e-15, atol=0)
+    np.testing.assert_array_equal(ge["basis"][:, 0], g.east)
+    np.testing.assert_array_equal(ge["basis"][:, 1], g.north)
+    np.testing.assert_allclose(ge["C"], g.C, rtol=0, atol=1e-13 * np.abs(g.C).max())
+    M.close()
+
+
+def test_errors_are_status_codes():
+    L = pa.lib()
+    h = ctypes.c_void_p()
+    for bad in [b"F8", b"O0", b"", b"O-3", b"Oxx", b"N32"]:
+        assert L.atlas_mesh_build(bad, 6371220.0, -1, ctypes.byref(h)) == -1
+        assert L.atlas_last_error()
+    assert L.atlas_mesh_build(b"O4", -1.0, -1, ctypes.byref(h)) == -1
+    assert L.atlas_mesh_build(b"O4", 1.0, -1, None) == -1
+    assert L.atlas_mesh_build(None, 1.0, -1, ctypes.byref(h)) == -1
+    assert L.atlas_mesh_build(b"O4", 1.0, -7, ctypes.byref(h)) == -4
+    assert L.atlas_mesh_sizes(None, None, None, None, None, None, None) == -1
+    L.atlas_mesh_free(None)
+    # operators on a host-only mesh or a NULL mesh
+    M = pa.Mesh("O4", device=-1)
+    buf = (ctypes.c_double * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.atlas_nabla_gradient(M.handle, 0, 1, p, p, None) == -4
+    assert L.atlas_nabla_gradient(None, 0, 1, p, p, None) == -1
+    assert L.atlas_nabla_conservation(M.handle, 0, 1, p, p, p, None) == -4
+    assert L.atlas_batch_create(M.handle, 1, None, 0, 1, None, ctypes.byref(h)) == -4
+    assert L.atlas_batch_run(None, None) == -1
+    assert L.atlas_nabla_set_tune(M.handle, 9, 1, None) == -5
+    assert L.atlas_nabla_set_tune(M.handle, 0, 3, None) == -1    # not a single op bit
+    bad = pa.TuneShape(waves_per_block=3)
+    assert L.atlas_nabla_set_tune(M.handle, 0, 1, ctypes.byref(bad)) == -1
+    assert L.atlas_nabla_set_tune(M.handle, 0, 1, None) == 0
+
+
+def test_no_device_is_reported():
+    if pa.device_count() > 0:
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert pa.lib().atlas_mesh_build(b"O4", 1.0, 0, ctypes.byref(h)) == -4
+    n = ctypes.c_int(5)
+    assert pa.lib().atlas_device_count(ctypes.byref(n)) == -4 and n.value == 0
+    with pytest.raises(pa.AtlasError) as e:
+        pa.Mesh("O4", device=0)
+    assert e.value.code == -4

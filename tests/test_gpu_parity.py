@@ -1,0 +1,203 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle.
+
+Bars (normwise relative L2, ||gpu - oracle|| / ||oracle||):
+  FP64: <= 1e-12.
+  FP32: <= 1e-5 against the oracle applied to the FP64 input (total error).
+  BF16 storage: <= 4e-3 against the oracle applied to the bf16-rounded input
+    (each output is rounded once to bfloat16, whose half-ulp is 2^-8 of the
+    value; FP32 arithmetic adds ~1e-6).  The total error against the FP64
+    input is printed, not bounded here.
+Sizes span several workgroups, ragged level tails (nlev not a multiple of 64)
+and every launch form: several nodes per wave (nlev <= 32) and one node per
+wave (nlev > 32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1908_07038_amd as pa
+import workloads as W
+from oracle import nabla
+from _oracle_cache import mesh_and_dual, coords
+
+pytestmark = pytest.mark.gpu
+
+R = 6371220.0
+DEV = torch.device("cuda", 0)
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5, torch.bfloat16: 4e-3}
+_MESHES = {}
+
+
+def gpu_mesh(N):
+    if N not in _MESHES:
+        _MESHES[N] = pa.Mesh(f"O{N}", radius=R, device=0)
+    return _MESHES[N]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+OPS = {
+    "gradient": (1, pa.gradient, nabla.gradient),
+    "divergence": (2, pa.divergence, nabla.divergence),
+    "laplacian": (1, pa.laplacian, nabla.laplacian),
+    "gradient_adjoint": (2, pa.gradient_adjoint, nabla.gradient_adjoint),
+    "divergence_adjoint": (1, pa.divergence_adjoint, nabla.divergence_adjoint),
+}
+
+
+def _input(N, L, comps, seed):
+    m, _ = mesh_and_dual(N)
+    if comps == 1:
+        # smooth content with a level-wise scale plus a little noise
+        s = W.sh_field(coords(m), min(12, 2 * N), seed)
+        return W.scaled_levels(s, L, 0.1) + W.normal((m.nnodes, L), seed + 1, 1e-3)
+    return W.normal((m.nnodes, L, 2), seed)
+
+
+def _run(name, N, L, dtype, seed=11):
+    comps, gpu_fn, ora_fn = OPS[name]
+    m, g = mesh_and_dual(N)
+    x = _input(N, L, comps, seed)
+    xt = torch.from_numpy(x).to(DEV).to(dtype)
+    y = gpu_fn(gpu_mesh(N), xt)
+    torch.cuda.synchronize()
+    xin = xt.double().cpu().numpy() if dtype == torch.bfloat16 else x
+    ref = ora_fn(m, g, xin)
+    return y.double().cpu().numpy(), ref, x, m, g
+
+
+CASES = [(4, 1), (4, 3), (32, 10), (32, 19), (32, 33), (32, 64), (32, 137), (1, 5), (2, 70)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", list(OPS))
+@pytest.mark.parametrize("N,L", CASES)
+def test_parity(name, N, L, dtype):
+    print(f"case {name} O{N} x {L} {dtype}", flush=True)
+    y, ref, x, m, g = _run(name, N, L, dtype)
+    err = rel(y, ref)
+    assert err <= TOL[dtype], (name, N, L, dtype, err)
+    if dtype == torch.bfloat16:
+        total = rel(y, OPS[name][2](m, g, x))
+        print(f"  bf16 kernel-only {err:.2e} total {total:.2e}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_config_o32(dtype):
+    """O32 x 10: SH sum to degree 10 with scale 1 + 0.1 k; grad, div(grad f), lap."""
+    M = gpu_mesh(32)
+    m, g = mesh_and_dual(32)
+    f = W.workload_o32(coords(m))
+    ft = torch.from_numpy(f).to(DEV).to(dtype)
+    gr = pa.gradient(M, ft)
+    dv = pa.divergence(M, gr)
+    lp = pa.laplacian(M, ft)
+    torch.cuda.synchronize()
+    og = nabla.gradient(m, g, f)
+    od = nabla.divergence(m, g, og)
+    ol = nabla.laplacian(m, g, f)
+    for y, r in [(gr, og), (dv, od), (lp, ol)]:
+        assert rel(y.double().cpu().numpy(), r) <= TOL[dtype]
+    # the fused and two-pass Laplacian agree with div(grad f) computed on the GPU
+    np.testing.assert_allclose(lp.double().cpu().numpy(), dv.double().cpu().numpy(),
+                               rtol=0, atol=TOL[dtype] * np.abs(ol).max() * 10)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_two_pass_laplacian(dtype):
+    M = gpu_mesh(32)
+    m, g = mesh_and_dual(32)
+    f = _input(32, 137, 1, 5)
+    ft = torch.from_numpy(f).to(DEV).to(dtype)
+    ws = torch.empty((M.nnodes, 137, 2), dtype=dtype, device=DEV)
+    l2 = pa.laplacian(M, ft, workspace=ws)
+    gr = pa.gradient(M, ft)
+    torch.cuda.synchronize()
+    assert torch.equal(ws, gr)               # the workspace holds the gradient
+    assert rel(l2.double().cpu().numpy(), nabla.laplacian(m, g, f)) <= TOL[dtype]
+
+
+def test_conservation_sums():
+    M = gpu_mesh(32)
+    m, g = mesh_and_dual(32)
+    uv = W.normal((m.nnodes, 37, 2), 3)
+    d = pa.divergence(M, torch.from_numpy(uv).to(DEV))
+    s, a = pa.conservation(M, d)
+    torch.cuda.synchronize()
+    os_, oa = nabla.conservation(m, g, d.cpu().numpy())
+    s, a = s.cpu().numpy(), a.cpu().numpy()
+    assert np.all(np.abs(s - os_) <= 1e-13 * oa)
+    np.testing.assert_allclose(a, oa, rtol=1e-13)
+    assert np.all(np.abs(s) <= 1e-13 * a)            # discrete Gauss theorem
+    # FP32 and BF16 inputs accumulate in FP64 too
+    for dt in (torch.float32, torch.bfloat16):
+        d2 = d.to(dt)
+        s2, a2 = pa.conservation(M, d2)
+        os2, oa2 = nabla.conservation(m, g, d2.double().cpu().numpy())
+        assert np.all(np.abs(s2.cpu().numpy() - os2) <= 1e-13 * oa2)
+        np.testing.assert_allclose(a2.cpu().numpy(), oa2, rtol=1e-13)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_deterministic_reruns(dtype):
+    M = gpu_mesh(32)
+    x = torch.from_numpy(_input(32, 137, 1, 9)).to(DEV).to(dtype)
+    w = torch.from_numpy(_input(32, 137, 2, 10)).to(DEV).to(dtype)
+    for fn, inp in [(pa.gradient, x), (pa.divergence, w), (pa.laplacian, x),
+                    (pa.gradient_adjoint, w), (pa.divergence_adjoint, x)]:
+        a = fn(M, inp)
+        b = fn(M, inp)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_gradient_of_constant_is_zero():
+    M = gpu_mesh(32)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        f = torch.full((M.nnodes, 65), 3.25, dtype=dt, device=DEV)
+        assert torch.count_nonzero(pa.gradient(M, f)).item() == 0
+        assert torch.count_nonzero(pa.laplacian(M, f)).item() == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_dot_product_identities(dtype):
+    M = gpu_mesh(32)
+    V, L = M.nnodes, 91
+    x = torch.from_numpy(W.normal((V, L), 1)).to(DEV).to(dtype)
+    y = torch.from_numpy(W.normal((V, L, 2), 2)).to(DEV).to(dtype)
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    lhs = (pa.gradient(M, x).double() * y.double()).sum().item()
+    rhs = (x.double() * pa.gradient_adjoint(M, y).double()).sum().item()
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    lhs = (pa.divergence(M, y).double() * x.double()).sum().item()
+    rhs = (y.double() * pa.divergence_adjoint(M, x).double()).sum().item()
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+
+
+def test_autograd_gradcheck():
+    M = gpu_mesh(4)
+    f = torch.from_numpy(W.normal((M.nnodes, 2), 4)).to(DEV).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: pa.grad(M, t), (f,), eps=1e-6, atol=1e-7)
+    uv = torch.from_numpy(W.normal((M.nnodes, 2, 2), 5)).to(DEV).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: pa.div(M, t), (uv,), eps=1e-6, atol=1e-7)
+    assert torch.autograd.gradcheck(lambda t: pa.lap(M, t), (f,), eps=1e-6, atol=1e-6)
+
+
+def test_argument_errors():
+    M = gpu_mesh(4)
+    f = torch.zeros((M.nnodes, 4), dtype=torch.float32, device=DEV)
+    g = torch.zeros((M.nnodes, 4, 2), dtype=torch.float32, device=DEV)
+    L = pa.lib()
+    assert L.atlas_nabla_gradient(M.handle, 1, 0, f.data_ptr(), g.data_ptr(), None) == -6
+    assert L.atlas_nabla_gradient(M.handle, 7, 4, f.data_ptr(), g.data_ptr(), None) == -5
+    assert L.atlas_nabla_gradient(M.handle, 1, 4, None, g.data_ptr(), None) == -1
+    assert L.atlas_nabla_gradient(M.handle, 1, 4, f.data_ptr() + 2, g.data_ptr(), None) == -1
+    assert L.atlas_nabla_gradient(M.handle, 1, 4, f.data_ptr(), g.data_ptr() + 4, None) == -1
+    assert L.atlas_nabla_gradient(M.handle, 1, 4, g.data_ptr(), g.data_ptr(), None) == -1   # overlap
+    with pytest.raises(ValueError):
+        pa.gradient(M, g)
+    torch.cuda.synchronize()

@@ -62,8 +62,13 @@ def _row_coefficients(coeffs, lmax, x, u):
     return A, B
 
 
-def sh_synthesis(coeffs, lmax, lon, sinlat, coslat, chunk=1 << 21):
-    """Evaluate sum c_lm Y_l^m at points given by lon, sin(lat), cos(lat)."""
+def sh_synthesis(coeffs, lmax, lon, sinlat, coslat, chunk=1 << 21, device=None):
+    """Evaluate sum c_lm Y_l^m at points given by lon, sin(lat), cos(lat).
+
+    The per-latitude Legendre stage runs in NumPy; the per-point sum over m
+    (Horner in exp(i lon)) runs in NumPy, or with torch on ``device`` when
+    given (then a float64 torch tensor on that device is returned).
+    """
     lon = np.asarray(lon, dtype=np.float64)
     xs, inv = np.unique(np.asarray(sinlat, dtype=np.float64), return_inverse=True)
     # one cos(lat) per distinct latitude
@@ -71,6 +76,17 @@ def sh_synthesis(coeffs, lmax, lon, sinlat, coslat, chunk=1 << 21):
     us[inv] = np.asarray(coslat, dtype=np.float64)
     A, B = _row_coefficients(coeffs, lmax, xs, us)
     Cm = (A - 1j * B)                       # [lmax+1, nrows]
+    if device is not None:
+        import torch
+        Ct = torch.from_numpy(Cm).to(device)
+        lt = torch.from_numpy(lon).to(device)
+        it = torch.from_numpy(inv.astype(np.int64)).to(device)
+        z = torch.polar(torch.ones_like(lt), lt)
+        acc = Ct[lmax][it].clone()
+        for m in range(lmax - 1, -1, -1):
+            acc.mul_(z)
+            acc.add_(Ct[m][it])
+        return acc.real.contiguous()
     out = np.empty(lon.size)
     for s0 in range(0, lon.size, chunk):
         s1 = min(lon.size, s0 + chunk)
@@ -84,9 +100,9 @@ def sh_synthesis(coeffs, lmax, lon, sinlat, coslat, chunk=1 << 21):
     return out
 
 
-def sh_field(coords, lmax, seed):
+def sh_field(coords, lmax, seed, device=None):
     """Seeded SH sum up to degree lmax at coords = (lon, sinlat, coslat)."""
-    return sh_synthesis(sh_coefficients(lmax, seed), lmax, *coords)
+    return sh_synthesis(sh_coefficients(lmax, seed), lmax, *coords, device=device)
 
 
 def real_sh(l, m, coords):
@@ -115,10 +131,13 @@ def workload_o320(coords, nlev=137, seed=1002, noise_seed=1012, sigma=1e-3):
     return f
 
 
-def workload_o1280(coords, nlev=137, seed=1003, lmax=256):
-    """SH sum up to degree 256 plus a level-wise linear trend rms(s) k/(L-1)."""
-    s = sh_field(coords, lmax, seed)
-    rms = math.sqrt(float(np.mean(s * s)))
+def workload_o1280(coords, nlev=137, seed=1003, lmax=256, device=None):
+    """SH sum up to degree 256 plus a level-wise linear trend rms(s) k/(L-1).
+
+    Returns (s, trend): f[i, k] = s[i] + trend[k].  With ``device`` the surface
+    s is a float64 torch tensor on that device."""
+    s = sh_field(coords, lmax, seed, device=device)
+    rms = math.sqrt(float((s * s).mean()))
     trend = rms * np.arange(nlev, dtype=np.float64) / max(1, nlev - 1)
     return s, trend
 
@@ -132,9 +151,9 @@ def batch_levels(ntracers=64, seed=1005):
     return np.random.default_rng(seed).choice(np.array(BATCH_LEVEL_CHOICES), ntracers)
 
 
-def tracer_surface(coords, t, lmax=128, base_seed=2000):
+def tracer_surface(coords, t, lmax=128, base_seed=2000, device=None):
     """Surface pattern of tracer t (degree <= 128, seed base + t)."""
-    return sh_field(coords, lmax, base_seed + t)
+    return sh_field(coords, lmax, base_seed + t, device=device)
 
 
 def tracer_field(s, nlev):
