@@ -1,0 +1,247 @@
+"""Benchmark of the median-dual Nabla hot path on one MI355X.
+
+Workload: O1280 octahedral mesh (6,599,680 nodes, 19,799,034 edges), 137
+levels, FP32 fields; input = seeded spherical-harmonic sum to degree 256 plus a
+level-wise linear trend (synthetic; the paper measures nothing and names no
+dataset).  One step = gradient f -> g, divergence g -> d, fused Laplacian
+f -> l, gradient adjoint g -> fT, divergence adjoint d -> gT, and the FP64
+conservation sums of d, all on one stream with inputs resident in HBM.
+
+value = edge-level updates per second = 6 E L / t_step (gradient, divergence
+and both adjoints count one sweep over the edges each, the Laplacian two).
+The same step is also timed in FP64 and with BF16 storage.
+
+Per-kernel durations come from HIP events recorded on the launch stream around
+every operator call inside the timed region; achieved bandwidth divides each
+kernel's algorithmic bytes (fields read once and written once, plus the
+minimal FP64 geometry of 104 bytes per node) by that duration.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu]
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+GEOM_BYTES_PER_NODE = 104  # S_e (24 B) + two int32 ends (8 B) per edge x 3 edges, + V_i (8 B)
+METRIC = "edge-level updates/s and % HBM peak, Nabla grad+div+lap O1280×137, FP32 vs FP64"
+UNIT = "edge-level updates/s"
+OPS = ["gradient", "divergence", "laplacian", "gradient_adjoint", "divergence_adjoint", "conservation"]
+# (elements read, elements written) per node-level, and edge sweeps
+OP_ELEMS = {"gradient": (1, 2), "divergence": (2, 1), "laplacian": (1, 1),
+            "gradient_adjoint": (2, 1), "divergence_adjoint": (1, 2), "conservation": (1, 0)}
+OP_SWEEPS = {"gradient": 1, "divergence": 1, "laplacian": 2, "gradient_adjoint": 1,
+             "divergence_adjoint": 1, "conservation": 0}
+KERNEL_NAME = {"gradient": "k_op<float, 0>", "divergence": "k_op<float, 1>",
+               "gradient_adjoint": "k_op<float, 2>", "divergence_adjoint": "k_op<float, 3>",
+               "laplacian": "k_op<float, 4>", "conservation": "k_cons_partial<float> + k_cons_final"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(op, V, L, esize):
+    r, w = OP_ELEMS[op]
+    geom = GEOM_BYTES_PER_NODE * V if op != "conservation" else 8 * V
+    return (r + w) * esize * V * L + geom
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_1908_07038_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(op, dtype_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        p = line.split()
+        if len(p) >= 5 and not line.startswith("#") and p[0] == src and p[1] == op and p[2] == dtype_name:
+            return float(p[3]) + float(p[4])
+    return None
+
+
+def run_gpu(args):
+    import torch
+
+    import paper_1908_07038_amd as pa
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    mesh = pa.Mesh(args.grid, radius=6371220.0, device=0)
+    V, E, L = mesh.nnodes, mesh.nedges, args.levels
+    log(f"mesh {args.grid}: V={V} E={E} built+uploaded in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    s, trend = W.workload_o1280(mesh.coords(), nlev=L, device=dev)
+    f64 = (s[:, None] + torch.from_numpy(trend).to(dev)[None, :]).contiguous()
+    del s
+    torch.cuda.synchronize()
+    log(f"input generated in {time.time() - t0:.1f}s")
+
+    results = {}
+    refs = {}
+    for dname, dtype, esize in (("f64", torch.float64, 8), ("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        f = f64.to(dtype)
+        g = torch.empty((V, L, 2), dtype=dtype, device=dev)
+        d = torch.empty((V, L), dtype=dtype, device=dev)
+        lp = torch.empty((V, L), dtype=dtype, device=dev)
+        fT = torch.empty((V, L), dtype=dtype, device=dev)
+        gT = torch.empty((V, L, 2), dtype=dtype, device=dev)
+        calls = {
+            "gradient": lambda: pa.gradient(mesh, f, out=g),
+            "divergence": lambda: pa.divergence(mesh, g, out=d),
+            "laplacian": lambda: pa.laplacian(mesh, f, out=lp),
+            "gradient_adjoint": lambda: pa.gradient_adjoint(mesh, g, out=fT),
+            "divergence_adjoint": lambda: pa.divergence_adjoint(mesh, d, out=gT),
+            "conservation": lambda: pa.conservation(mesh, d),
+        }
+        for _ in range(args.warmup):
+            for op in OPS:
+                calls[op]()
+        torch.cuda.synchronize()
+        ev = {op: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)] for op in OPS}
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            for op in OPS:
+                a, b = ev[op][k]
+                a.record()
+                calls[op]()
+                b.record()
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t_start) / args.steps
+        per_op = {}
+        for op in OPS:
+            ms = sum(a.elapsed_time(b) for a, b in ev[op]) / args.steps
+            by = alg_bytes(op, V, L, esize)
+            per_op[op] = {"ms": round(ms, 4), "alg_GB": round(by / 1e9, 3),
+                          "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3)}
+            if OP_SWEEPS[op]:
+                per_op[op]["edge_updates_s"] = float(f"{OP_SWEEPS[op] * E * L / (ms * 1e-3):.4g}")
+        cs, ca = calls["conservation"]()
+        cons = float((cs.abs() / ca).max().item())
+        outs = {"gradient": g, "divergence": d, "laplacian": lp, "gradient_adjoint": fT,
+                "divergence_adjoint": gT}
+        if dname == "f64":
+            refs = {k: v.clone() for k, v in outs.items()}
+        err = {}
+        for k, v in outs.items():
+            r = refs[k]
+            err[k] = float(f"{(torch.linalg.vector_norm((v.double() - r).flatten()) / torch.linalg.vector_norm(r.flatten())).item():.3g}")
+        sweeps = sum(OP_SWEEPS.values())
+        results[dname] = {"ms_per_step": round(t_step * 1e3, 4),
+                          "edge_updates_s": float(f"{sweeps * E * L / t_step:.4g}"),
+                          "per_op": per_op, "rel_l2_vs_f64": err, "conservation_max_rel": cons}
+        log(f"{dname}: {t_step * 1e3:.3f} ms/step, " +
+            ", ".join(f"{op} {per_op[op]['ms']:.3f}ms {per_op[op]['hbm_frac'] * 100:.0f}%" for op in OPS))
+        del f, g, d, lp, fT, gT, outs
+        torch.cuda.empty_cache()
+    del refs, f64
+    torch.cuda.empty_cache()
+    return mesh, results
+
+
+def run_cpu_baseline(grid, levels, nlev_sample, gpu_mesh_coords=None):
+    """Time the FP64 oracle (as it stands) on a level sample of the same
+    workload: same mesh, first `nlev_sample` levels, one full step."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    from oracle import nabla
+
+    t0 = time.time()
+    m = oracle.build_mesh(grid)
+    geo = oracle.build_dual(m)
+    log(f"oracle mesh {grid} built in {time.time() - t0:.1f}s")
+    co = (m.grid.lon, m.grid.sinlat, m.grid.coslat)
+    s, trend = W.workload_o1280(co, nlev=levels)
+    f = s[:, None] + trend[None, :nlev_sample]
+    t0 = time.perf_counter()
+    g = nabla.gradient(m, geo, f)
+    d = nabla.divergence(m, geo, g)
+    nabla.laplacian(m, geo, f)
+    nabla.gradient_adjoint(m, geo, g)
+    nabla.divergence_adjoint(m, geo, d)
+    nabla.conservation(m, geo, d)
+    t = time.perf_counter() - t0
+    E = m.nedges
+    log(f"oracle step on {nlev_sample} levels: {t:.1f}s")
+    return {"value": float(f"{6 * E * nlev_sample / t:.4g}"), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"one full step (grad, div, lap, both adjoints, conservation) of the FP64 NumPy oracle "
+                      f"on the {grid} mesh, levels 0..{nlev_sample - 1} of the {levels}-level workload; "
+                      f"single process (NumPy bincount scatter is single-threaded)",
+            "seconds": round(t, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--grid", default="O1280")
+    ap.add_argument("--levels", type=int, default=137)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
+              "multi-GPU path (levels and tracers would shard with no communication). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    mesh, res = run_gpu(args)
+    V, E, L = mesh.nnodes, mesh.nedges, args.levels
+    f32 = res["f32"]
+    dom = max((op for op in OPS), key=lambda op: f32["per_op"][op]["ms"])
+    dms = f32["per_op"][dom]["ms"]
+    dbytes = alg_bytes(dom, V, L, 4)
+    traffic = measured_traffic(dom, "f32")
+    roof = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "op": dom,
+            "achieved": round(dbytes / (dms * 1e-3) / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(dbytes / (dms * 1e-3) / HBM_PEAK, 4),
+            "alg_bytes_per_launch": dbytes,
+            "traffic": traffic}
+    cpu = None
+    if not args.skip_cpu:
+        cpu = run_cpu_baseline(args.grid, L, args.cpu_levels)
+    out = {
+        "metric": METRIC, "value": f32["edge_updates_s"], "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded SH degree 256 + level trend)",
+        "config": {"workload": f"{args.grid} x {L} levels, FP32 fields, FP64 geometry: grad, div, fused lap, "
+                               "grad adjoint, div adjoint, FP64 conservation", "nnodes": V, "nedges": E,
+                   "nlev": L, "edge_updates_per_step": 6 * E * L},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64": {"ms_per_step": res["f64"]["ms_per_step"], "edge_updates_s": res["f64"]["edge_updates_s"]},
+        "bf16": {"ms_per_step": res["bf16"]["ms_per_step"], "edge_updates_s": res["bf16"]["edge_updates_s"]},
+        "f32_speedup_over_f64": round(res["f64"]["ms_per_step"] / f32["ms_per_step"], 3),
+        "detail": res,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -22,6 +22,7 @@
  *     the element size (scalars) or twice the element size (vectors).
  *   - Outputs are overwritten, never accumulated into; an output may not
  *     overlap its input (the operators gather neighbour values).
+ *   - nnodes * nlev must not exceed 2^32 - 1 (ATLAS_ESHAPE otherwise).
  *   - `stream` is a hipStream_t of the mesh's device passed as void*
  *     (NULL = the default stream).  Operator calls are asynchronous on it.
  *   - Node order, edge order and the dual geometry are defined by
@@ -200,10 +201,17 @@ typedef struct {
 
 /* Launch shape.  Zero fields mean "library default". */
 typedef struct {
-  int32_t waves_per_block;  /* 1, 2, 4, 8 or 16                             */
-  int32_t nodes_per_wave;   /* consecutive nodes a wave handles per item     */
+  int32_t waves_per_block;  /* 1, 2 or 4                                    */
+  int32_t nodes_per_wave;   /* node groups a wave handles per workgroup       */
   int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CU count     */
-  int32_t xcd_remap;        /* 1: give each XCD a contiguous slice of work    */
+  int32_t xcd_remap;        /* 1: each XCD walks a contiguous part of the
+                               node order (the default), 2: plain order      */
+  int32_t lanes_per_node;   /* 16, 32 or 64 lanes share a column (nlev > 32);
+                               columns of <= 32 levels always use nlev lanes */
+  int32_t slices_per_iter;  /* level slices in flight per lane, 1..3         */
+  int32_t band_rows;        /* rows per band of the node processing order:
+                               nodes of a band are visited by longitude so
+                               rows above and below stay in cache            */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;
@@ -249,7 +257,9 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
                      atlas_tune_t* best, float* best_ms);
 
 /* Set the launch shape used by the single-field calls for (op, dtype) on this
- * mesh; NULL restores the default.  op: one ATLAS_OP_* bit. */
+ * mesh; NULL restores the default.  op: one ATLAS_OP_* bit.  A band height
+ * not used before on this mesh builds its node order on the next call (host
+ * work plus one device allocation of 4 bytes per node). */
 int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op,
                          const atlas_tune_t* tune);
 

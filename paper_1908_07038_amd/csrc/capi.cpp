@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -69,6 +70,8 @@ struct atlas_mesh_s {
   double* scratch = nullptr;
   size_t scratch_bytes = 0;
   Shape shape[OP_COUNT][3];
+  std::mutex order_mu;
+  std::map<int, const int32_t*> orders;   // band rows -> device node order
 
   ~atlas_mesh_s() {
     if (device >= 0) {
@@ -93,6 +96,18 @@ struct atlas_mesh_s {
   }
 
   const DevTables& tables(int dtype) const { return dtype == ATLAS_F64 ? tab64 : tab32; }
+
+  // Device node order for a band height, built and uploaded on first use.
+  const int32_t* order(int band_rows) {
+    std::lock_guard<std::mutex> lk(order_mu);
+    auto it = orders.find(band_rows);
+    if (it != orders.end()) return it->second;
+    std::vector<int32_t> ord;
+    build_band_order(host, band_rows, ord);
+    const int32_t* d = upload(ord);
+    orders[band_rows] = d;
+    return d;
+  }
 };
 
 namespace {
@@ -155,11 +170,21 @@ int check_field(const void* p, size_t comps, size_t esize, const char* name) {
   return ATLAS_OK;
 }
 
+void shape_out(const Shape& s, atlas_tune_t* t) {
+  t->waves_per_block = s.waves_per_block;
+  t->nodes_per_wave = s.nodes_per_wave;
+  t->blocks_per_cu = s.blocks_per_cu;
+  t->xcd_remap = s.xcd_remap ? 1 : 2;
+  t->lanes_per_node = s.lanes_per_node;
+  t->slices_per_iter = s.slices_per_iter;
+  t->band_rows = s.band_rows;
+}
+
 int check_shape(Shape& s, const atlas_tune_t* t) {
   if (!t) return ATLAS_OK;
   if (t->waves_per_block) {
     const int w = t->waves_per_block;
-    if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16) return fail(ATLAS_EINVAL, "waves_per_block must be 1,2,4,8,16");
+    if (w != 1 && w != 2 && w != 4) return fail(ATLAS_EINVAL, "waves_per_block must be 1, 2 or 4");
     s.waves_per_block = w;
   }
   if (t->nodes_per_wave) {
@@ -170,8 +195,15 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(ATLAS_EINVAL, "blocks_per_cu must be 1..64");
     s.blocks_per_cu = t->blocks_per_cu;
   }
-  if (t->xcd_remap < 0 || t->xcd_remap > 1) return fail(ATLAS_EINVAL, "xcd_remap must be 0 or 1");
-  s.xcd_remap = t->xcd_remap;
+  if (t->xcd_remap < 0 || t->xcd_remap > 2) return fail(ATLAS_EINVAL, "xcd_remap must be 0, 1 or 2");
+  if (t->xcd_remap) s.xcd_remap = t->xcd_remap == 1 ? 1 : 0;
+  const int p = t->lanes_per_node;
+  if (p != 0 && p != 16 && p != 32 && p != 64) return fail(ATLAS_EINVAL, "lanes_per_node must be 0, 16, 32 or 64");
+  s.lanes_per_node = p;
+  if (t->slices_per_iter < 0 || t->slices_per_iter > 3) return fail(ATLAS_EINVAL, "slices_per_iter must be 0..3");
+  s.slices_per_iter = t->slices_per_iter;
+  if (t->band_rows < 0 || t->band_rows > 65536) return fail(ATLAS_EINVAL, "band_rows must be 0..65536");
+  s.band_rows = t->band_rows;
   return ATLAS_OK;
 }
 
@@ -183,7 +215,8 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
   if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
   const int64_t V = mesh->host.V;
-  if ((int64_t)nlev > (int64_t)INT32_MAX / 2) return fail(ATLAS_ESHAPE, "nlev too large");
+  // node-level indices are 32-bit inside the kernels
+  if ((int64_t)nlev * V > (int64_t)UINT32_MAX) return fail(ATLAS_ESHAPE, "nnodes * nlev exceeds 2^32 - 1");
   if ((rc = check_field(in, kInComps[op], es, "input"))) return rc;
   if ((rc = check_field(out, kOutComps[op], es, "output"))) return rc;
   const size_t nin = (size_t)V * nlev * kInComps[op] * es;
@@ -192,7 +225,15 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
   const Shape& sh = shape_override ? *shape_override : mesh->shape[op][dtype];
-  hipError_t e = launch_op(op, dtype, mesh->tables(dtype), V, nlev, in, out, sh, (hipStream_t)stream);
+  const int32_t* order = nullptr;
+  try {
+    order = mesh->order(band_rows_of(sh));
+  } catch (const std::bad_alloc&) {
+    return fail(ATLAS_ENOMEM, "cannot allocate the node order");
+  } catch (const std::exception& ex) {
+    return fail(ATLAS_EHIP, ex.what());
+  }
+  hipError_t e = launch_op(op, dtype, mesh->tables(dtype), order, V, nlev, in, out, sh, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, kOpName[op]);
   return ATLAS_OK;
 }
@@ -417,7 +458,7 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
   if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit");
   if (reps < 1 || reps > 10000) return fail(ATLAS_EINVAL, "reps must be 1..10000");
   if (!best) return fail(ATLAS_EINVAL, "best is NULL");
-  // argument check through a normal call with the default shape
+  // argument check through a normal call with the current shape
   if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream))) return rc;
   DeviceGuard g(mesh->device);
   hipStream_t st = (hipStream_t)stream;
@@ -428,37 +469,63 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
     return fail(ATLAS_EHIP, "hipEventCreate");
   }
   float bestt = 1e30f;
-  Shape bs = mesh->shape[o][dtype];
-  const int wpbs[] = {1, 2, 4, 8};
-  const int npws[] = {1, 2, 4, 8};
-  for (int w : wpbs)
-    for (int n : npws)
-      for (int x = 0; x < 2; ++x) {
+  Shape bs = Shape();
+  auto time_shape = [&](const Shape& s) -> int {
+    int r = run_op(mesh, o, dtype, nlev, in, out, stream, &s);
+    if (r) return r;
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i)
+      if ((r = run_op(mesh, o, dtype, nlev, in, out, stream, &s))) return r;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(ATLAS_EHIP, "hipEventSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (ms < bestt) {
+      bestt = ms;
+      bs = s;
+    }
+    return ATLAS_OK;
+  };
+  // stage 1: column mapping (lanes per node, slices per iteration)
+  {
+    const int ps[] = {16, 32, 64};
+    for (int p : ps) {
+      if (nlev <= 32 && p != 16) continue;   // short columns always use nlev lanes
+      for (int u = 1; u <= 3; ++u) {
         Shape s;
-        s.waves_per_block = w;
-        s.nodes_per_wave = n;
-        s.xcd_remap = x;
-        if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream, &s))) goto done;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps; ++r)
-          if ((rc = run_op(mesh, o, dtype, nlev, in, out, stream, &s))) goto done;
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-          rc = fail(ATLAS_EHIP, "hipEventSynchronize");
-          goto done;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)reps;
-        if (ms < bestt) {
-          bestt = ms;
-          bs = s;
-        }
+        s.lanes_per_node = nlev <= 32 ? 0 : p;
+        s.slices_per_iter = u;
+        if ((rc = time_shape(s))) goto done;
       }
-  best->waves_per_block = bs.waves_per_block;
-  best->nodes_per_wave = bs.nodes_per_wave;
-  best->blocks_per_cu = bs.blocks_per_cu;
-  best->xcd_remap = bs.xcd_remap;
+    }
+  }
+  // stage 2: workgroup shape and XCD remapping around the best mapping
+  {
+    const Shape base = bs;
+    const int wpbs[] = {1, 2, 4};
+    const int npws[] = {1, 2, 4, 8};
+    for (int w : wpbs)
+      for (int n : npws)
+        for (int x = 0; x < 2; ++x) {
+          Shape s = base;
+          s.waves_per_block = w;
+          s.nodes_per_wave = n;
+          s.xcd_remap = x;
+          if ((rc = time_shape(s))) goto done;
+        }
+  }
+  // stage 3: band height of the node order
+  {
+    const Shape base = bs;
+    const int hs[] = {8, 16, 64, 128};
+    for (int h : hs) {
+      Shape s = base;
+      s.band_rows = h;
+      if ((rc = time_shape(s))) goto done;
+    }
+  }
+  shape_out(bs, best);
   if (best_ms) *best_ms = bestt;
 done:
   (void)hipEventDestroy(e0);
@@ -472,6 +539,7 @@ done:
 
 struct atlas_batch_s {
   atlas_mesh_t mesh = nullptr;
+  const int32_t* order = nullptr;   // owned by the mesh
   int dtype = 0;
   uint32_t mask = 0;
   Shape shape;
@@ -503,6 +571,13 @@ namespace {
 // (Re)build the device work tables of a plan for its current shape.
 int plan_upload(atlas_batch_s* b) {
   const int64_t V = b->mesh->host.V;
+  try {
+    b->order = b->mesh->order(band_rows_of(b->shape));
+  } catch (const std::bad_alloc&) {
+    return fail(ATLAS_ENOMEM, "cannot allocate the node order");
+  } catch (const std::exception& ex) {
+    return fail(ATLAS_EHIP, ex.what());
+  }
   for (int o = 0; o < 4; ++o) {
     if (b->items[o]) {
       (void)hipFree(b->items[o]);
@@ -516,7 +591,9 @@ int plan_upload(atlas_batch_s* b) {
       host[t].in = b->descs[t].in[o];
       host[t].out = b->descs[t].out[o];
       host[t].nlev = L;
-      host[t].pack = pack_factor(L);
+      host[t].lanes = lanes_per_node(L, b->shape);
+      host[t].unroll = slices_per_iter(L, b->shape);
+      host[t].reserved = 0;
       host[t].tile_begin = tile;
       tile += tiles_for(V, L, b->shape);
     }
@@ -537,8 +614,8 @@ int plan_run(atlas_batch_s* b, hipStream_t st, const Shape& sh) {
   const int64_t V = b->mesh->host.V;
   for (int o = 0; o < 4; ++o) {
     if (!(b->mask & (1u << o))) continue;
-    hipError_t e = launch_batched(o, b->dtype, b->mesh->tables(b->dtype), V, b->items[o], (int)b->descs.size(),
-                                  b->total[o], sh, b->mesh->num_cus, st);
+    hipError_t e = launch_batched(o, b->dtype, b->mesh->tables(b->dtype), b->order, V, b->items[o],
+                                  (int)b->descs.size(), b->total[o], sh, b->mesh->num_cus, st);
     if (e != hipSuccess) return hip_fail(e, kOpName[o]);
   }
   return ATLAS_OK;
@@ -562,6 +639,8 @@ int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* 
     const atlas_tracer_desc_t& d = descs[t];
     if (d.nlev < 1 || d.reserved != 0)
       return fail(ATLAS_ESHAPE, "tracer " + std::to_string(t) + ": nlev must be >= 1 and reserved 0");
+    if ((int64_t)d.nlev * mesh->host.V > (int64_t)UINT32_MAX)
+      return fail(ATLAS_ESHAPE, "tracer " + std::to_string(t) + ": nnodes * nlev exceeds 2^32 - 1");
     for (int o = 0; o < 4; ++o) {
       if (!(op_mask & (1u << o))) continue;
       const std::string nm = "tracer " + std::to_string(t) + " " + kOpName[o];
@@ -651,7 +730,7 @@ int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_
   Shape bs = orig;
   float bestt = 1e30f;
   int rc = ATLAS_OK;
-  const int wpbs[] = {2, 4, 8};
+  const int wpbs[] = {2, 4};
   const int npws[] = {1, 2, 4};
   const int bpcs[] = {2, 4, 8};
   for (int w : wpbs)
@@ -677,10 +756,7 @@ int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_
           ms /= (float)reps;
           if (ms < bestt) { bestt = ms; bs = s; }
         }
-  best->waves_per_block = bs.waves_per_block;
-  best->nodes_per_wave = bs.nodes_per_wave;
-  best->blocks_per_cu = bs.blocks_per_cu;
-  best->xcd_remap = bs.xcd_remap;
+  shape_out(bs, best);
   if (best_ms) *best_ms = bestt;
 done:
   // leave the plan with the best shape found (or its original one on error)

@@ -5,21 +5,30 @@
 // node by node): the output element (node i, level k) is written by exactly
 // one lane, neighbour values are read in a fixed slot order, and nothing is
 // accumulated across lanes, so there are no atomics and reruns are bitwise
-// identical.  The path is a sparse stencil whose dense dimension is the
-// level column, so it is bound by HBM traffic and uses no matrix cores.
+// identical.  The path is a sparse stencil whose dense dimension is the level
+// column, so it is bound by memory traffic and uses no matrix cores.
 //
-// Mapping.  Fields are [node][level] with levels innermost.  For columns of
-// more than 32 levels one 64-lane wave owns one node and sweeps its column in
-// slices of 64 consecutive levels: the node's table row (neighbour indices
-// and coefficient pairs) is wave-uniform, so it is fetched once through the
-// scalar cache and held in scalar registers, and each neighbour read is one
-// contiguous 64-element vector load.  Short columns (<= 32 levels) pack
-// floor(64 / nlev) nodes into one wave, one (node, level) per lane.
+// Mapping.  Fields are [node][level] with levels innermost.  A 64-lane wave
+// owns G = 64 / P nodes at a time, P lanes per node; lane t of a node handles
+// levels t, t + P, t + 2P, ... of its column.  P is chosen per level count so
+// that the column fills the lanes well (P = nlev for columns of at most 32
+// levels, else 64, 32 or 16, e.g. 16 lanes x 9 slices for 137 levels).  The
+// lane -> node assignment is fixed, so each lane reads its node's table row
+// (neighbour offsets and coefficient pairs) once and keeps it in registers for
+// the whole column.  U level slices are processed per iteration with all
+// neighbour loads issued before any arithmetic, which keeps many independent
+// loads in flight per wave; loads of slices past the column end are clamped
+// to the last level (cache hits) and their results are not stored.
 //
-// XCD awareness.  Workgroups are dispatched round-robin over the eight XCDs;
-// with remapping on, workgroup b works on logical block
-// (b mod 8) * ceil(nblocks / 8) + b / 8, so each XCD walks a contiguous band
-// of latitude rows and the rows above and below a band stay in its own L2.
+// Cache reuse.  Each node value is read by the node and its ~6 neighbours,
+// two of them in the row above and two in the row below; at 137 FP32 levels
+// three rows of the O1280 grid already exceed an XCD's 4 MB L2.  Work
+// therefore follows a node order built on the host: bands of rows, nodes of a
+// band sorted by longitude, so the rows above and below are touched at the
+// same longitude at about the same time.  Workgroups are dispatched
+// round-robin over the eight XCDs; with remapping on, workgroup b works on
+// logical block (b mod 8) * ceil(nblocks / 8) + b / 8, so each XCD walks a
+// contiguous part of the order (whole bands) in its own L2.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -30,7 +39,7 @@ namespace {
 
 using bf16_t = uint16_t;
 
-constexpr int kLapMax = 24;   // two-ring table stride the kernels are built for
+constexpr int kLapStride = 24;   // two-ring record: up to 23 entries + the count
 
 template <class S> struct Traits;
 template <> struct Traits<double> { using C = double; using C2 = double2; };
@@ -58,260 +67,212 @@ __device__ __forceinline__ float2 ld2(const bf16_t* p) {
   return make_float2(bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16));
 }
 
-__device__ __forceinline__ void st1(double* p, double v) { *p = v; }
-__device__ __forceinline__ void st1(float* p, float v) { *p = v; }
-__device__ __forceinline__ void st1(bf16_t* p, float v) { *p = (bf16_t)f32_to_bf16(v); }
+// Outputs are written once and not read again by the kernel: non-temporal
+// stores keep them from displacing the neighbour rows held in L2.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void st1(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st1(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st1(bf16_t* p, float v) {
+  __builtin_nontemporal_store((bf16_t)f32_to_bf16(v), p);
+}
 
 __device__ __forceinline__ void st2(double* p, double x, double y) {
-  *reinterpret_cast<double2*>(p) = make_double2(x, y);
+  __builtin_nontemporal_store(f64x2{x, y}, reinterpret_cast<f64x2*>(p));
 }
 __device__ __forceinline__ void st2(float* p, float x, float y) {
-  *reinterpret_cast<float2*>(p) = make_float2(x, y);
+  __builtin_nontemporal_store(f32x2{x, y}, reinterpret_cast<f32x2*>(p));
 }
 __device__ __forceinline__ void st2(bf16_t* p, float x, float y) {
-  *reinterpret_cast<uint32_t*>(p) = f32_to_bf16(x) | (f32_to_bf16(y) << 16);
-}
-
-// Read-only table data read through the constant address space: with a
-// wave-uniform address the compiler fetches it with scalar loads into scalar
-// registers.  Valid because no kernel writes the tables.
-template <class T>
-__device__ __forceinline__ T ld_const(const T* p) {
-  return *(const __attribute__((address_space(4))) T*)(p);
-}
-__device__ __forceinline__ int32_t ld_uniform(const int32_t* p) { return ld_const(p); }
-__device__ __forceinline__ float ld_uniform(const float* p) { return ld_const(p); }
-__device__ __forceinline__ double ld_uniform(const double* p) { return ld_const(p); }
-__device__ __forceinline__ float2 ld_uniform(const float2* p) {
-  const float* q = reinterpret_cast<const float*>(p);
-  return make_float2(ld_const(q), ld_const(q + 1));
-}
-__device__ __forceinline__ double2 ld_uniform(const double2* p) {
-  const double* q = reinterpret_cast<const double*>(p);
-  return make_double2(ld_const(q), ld_const(q + 1));
+  __builtin_nontemporal_store(f32_to_bf16(x) | (f32_to_bf16(y) << 16), reinterpret_cast<uint32_t*>(p));
 }
 
 struct Args {
-  const int32_t* nbr;   // nbr8 or the two-ring neighbour table
-  const void* coef;     // coefficient pairs or two-ring weights
-  int stride;           // entries per node row of nbr/coef
+  const int32_t* order; // [V] node processing order (a permutation)
+  const int32_t* nbr;   // [V][8] neighbour table or [V][24] two-ring table
+  const void* coef;     // coefficient pairs or two-ring weights (same row layout)
   const void* in;
   void* out;
   int64_t V;
   int32_t L;            // levels
-  int32_t pack;         // 0: one node per wave, else nodes per wave
-  int32_t npw;          // nodes (or node groups) per wave per block
+  int32_t P;            // lanes per node (64 / P nodes per wave)
+  int32_t npw;          // node groups per wave per workgroup
 };
 
-// ---- per-element arithmetic (shared by every launch form) -------------------
+// ---- one node group per wave --------------------------------------------------
 //
-// NS is the number of table entries a node uses (its degree, or its two-ring
-// size for the Laplacian), fixed at compile time so that all neighbour loads
-// of an element are issued back to back before any arithmetic waits on them.
-// Entries are consumed in slot order, which fixes the summation order.
+// NS: table entries read per node (7 = every slot, padded with the node itself
+// and zero coefficients; 6 when every node of the wave has degree 6; 23 or 18
+// for the two-ring table).  Padding entries add exact zeros.  Entries are
+// consumed in slot order, which fixes the summation order of every element.
 
-// gradient, difference form: sum_s (a, b)_s (f_n - f_i)
-template <class S, int NS>
-__device__ __forceinline__ void elem_grad(const S* __restrict__ in, S* __restrict__ out, int64_t L,
-                                          int64_t node, int k, const int32_t* nb,
-                                          const typename Traits<S>::C2* cf) {
-  using C = typename Traits<S>::C;
-  C v[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) v[s] = ld1(in + (int64_t)nb[s] * L + k);
-  const C fi = ld1(in + node * L + k);
-  C ax = 0, ay = 0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const C d = v[s] - fi;
-    ax = fma(cf[s].x, d, ax);
-    ay = fma(cf[s].y, d, ay);
-  }
-  st2(out + 2 * (node * L + k), ax, ay);
-}
-
-// divergence adjoint: (A, B)_i d_i + sum_s (c, d)_{n,rev} d_n
-template <class S, int NS>
-__device__ __forceinline__ void elem_divT(const S* __restrict__ in, S* __restrict__ out, int64_t L,
-                                          int64_t node, int k, const int32_t* nb,
-                                          const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
-  using C = typename Traits<S>::C;
-  C v[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) v[s] = ld1(in + (int64_t)nb[s] * L + k);
-  const C di = ld1(in + node * L + k);
-  C ax = dg.x * di, ay = dg.y * di;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    ax = fma(cf[s].x, v[s], ax);
-    ay = fma(cf[s].y, v[s], ay);
-  }
-  st2(out + 2 * (node * L + k), ax, ay);
-}
-
-// divergence and gradient adjoint: (x, y)_diag . in_i + sum_s (x, y)_s . in_n
-template <class S, int NS>
-__device__ __forceinline__ void elem_v2s(const S* __restrict__ in, S* __restrict__ out, int64_t L,
-                                         int64_t node, int k, const int32_t* nb,
-                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
+template <class S, int OP, int NS, int U>
+__device__ __forceinline__ void run_1ring(const Args& a, int64_t nd, bool ok, int t) {
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
-  C2 v[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) v[s] = ld2(in + 2 * ((int64_t)nb[s] * L + k));
-  const C2 ui = ld2(in + 2 * (node * L + k));
-  C acc = dg.x * ui.x;
-  acc = fma(dg.y, ui.y, acc);
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    acc = fma(cf[s].x, v[s].x, acc);
-    acc = fma(cf[s].y, v[s].y, acc);
-  }
-  st1(out + node * L + k, acc);
-}
-
-// fused Laplacian over the two-ring: sum_m W_im (f_m - f_i)
-template <class S, int NS>
-__device__ __forceinline__ void elem_lap(const S* __restrict__ in, S* __restrict__ out, int64_t L,
-                                         int64_t node, int k, const int32_t* nb,
-                                         const typename Traits<S>::C* w) {
-  using C = typename Traits<S>::C;
-  C v[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) v[s] = ld1(in + (int64_t)nb[s] * L + k);
-  const C fi = ld1(in + node * L + k);
-  C acc = 0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) acc = fma(w[s], v[s] - fi, acc);
-  st1(out + node * L + k, acc);
-}
-
-template <class S, int OP, int NS>
-__device__ __forceinline__ void elem_1ring(const Args& a, int64_t node, int k, const int32_t* nb,
-                                           const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
-  const S* in = static_cast<const S*>(a.in);
-  S* out = static_cast<S*>(a.out);
-  if constexpr (OP == OP_GRAD) elem_grad<S, NS>(in, out, a.L, node, k, nb, cf);
-  else if constexpr (OP == OP_DIVT) elem_divT<S, NS>(in, out, a.L, node, k, nb, cf, dg);
-  else elem_v2s<S, NS>(in, out, a.L, node, k, nb, cf, dg);
-}
-
-// ---- one node per wave (columns of more than 32 levels) ---------------------
-//
-// The node's table row is wave-uniform: it is read once, kept in registers,
-// and reused for every 64-level slice of the column.
-
-template <class S, int OP, int NS>
-__device__ __forceinline__ void slab_1ring(const Args& a, int64_t node, int lane) {
-  using C2 = typename Traits<S>::C2;
-  const int32_t* nbp = a.nbr + node * 8;
-  const C2* cfp = static_cast<const C2*>(a.coef) + node * 8;
-  int nb[NS];
+  const int32_t* nbp = a.nbr + nd * 8;
+  const C2* cfp = static_cast<const C2*>(a.coef) + nd * 8;
+  const uint32_t L = (uint32_t)a.L;
+  uint32_t off[NS];
   C2 cf[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    nb[s] = ld_uniform(nbp + s);
-    cf[s] = ld_uniform(cfp + s);
+    off[s] = (uint32_t)nbp[s] * L;
+    cf[s] = cfp[s];
   }
-  const C2 dg = ld_uniform(cfp + 7);
-  for (int k0 = 0; k0 < a.L; k0 += 64) {
-    const int k = k0 + lane;
-    if (k < a.L) elem_1ring<S, OP, NS>(a, node, k, nb, cf, dg);
+  const C2 dg = cfp[7];
+  const uint32_t self = (uint32_t)nd * L;
+  const S* __restrict__ in = static_cast<const S*>(a.in);
+  S* __restrict__ out = static_cast<S*>(a.out);
+  const int P = a.P;
+  const int nsl = (a.L + P - 1) / P;
+  for (int r0 = 0; r0 < nsl; r0 += U) {
+    uint32_t kc[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t k = (uint32_t)(t + P * (r0 + u));
+      st[u] = ok && k < L;
+      kc[u] = k < L ? k : L - 1;
+    }
+    if constexpr (OP == OP_GRAD || OP == OP_DIVT) {
+      C v[U][NS], x0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v[u][s] = ld1(in + (size_t)(off[s] + kc[u]));
+        x0[u] = ld1(in + (size_t)(self + kc[u]));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        C ax, ay;
+        if constexpr (OP == OP_GRAD) {
+          // difference form: sum_s (a, b)_s (f_n - f_i)
+          ax = 0;
+          ay = 0;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const C d = v[u][s] - x0[u];
+            ax = fma(cf[s].x, d, ax);
+            ay = fma(cf[s].y, d, ay);
+          }
+        } else {
+          // divergence adjoint: (A, B)_i d_i + sum_s (c, d)_{n,rev} d_n
+          ax = dg.x * x0[u];
+          ay = dg.y * x0[u];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            ax = fma(cf[s].x, v[u][s], ax);
+            ay = fma(cf[s].y, v[u][s], ay);
+          }
+        }
+        if (st[u]) st2(out + 2 * (size_t)(self + kc[u]), ax, ay);
+      }
+    } else {
+      // divergence and gradient adjoint: diag . in_i + sum_s (x, y)_s . in_n
+      C2 v[U][NS], x0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v[u][s] = ld2(in + 2 * (size_t)(off[s] + kc[u]));
+        x0[u] = ld2(in + 2 * (size_t)(self + kc[u]));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        C acc = dg.x * x0[u].x;
+        acc = fma(dg.y, x0[u].y, acc);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          acc = fma(cf[s].x, v[u][s].x, acc);
+          acc = fma(cf[s].y, v[u][s].y, acc);
+        }
+        if (st[u]) st1(out + (size_t)(self + kc[u]), acc);
+      }
+    }
   }
 }
 
-template <class S, int NS>
-__device__ __forceinline__ void slab_lap(const Args& a, int64_t node, int lane) {
+// fused Laplacian over the two-ring: sum_m W_im (f_m - f_i)
+template <class S, int NS, int U>
+__device__ __forceinline__ void run_lap(const Args& a, int64_t nd, bool ok, int t) {
   using C = typename Traits<S>::C;
-  const int32_t* nbp = a.nbr + node * a.stride;
-  const C* wp = static_cast<const C*>(a.coef) + node * a.stride;
-  int nb[NS];
+  const int32_t* nbp = a.nbr + nd * kLapStride;
+  const C* wp = static_cast<const C*>(a.coef) + nd * kLapStride;
+  const uint32_t L = (uint32_t)a.L;
+  uint32_t off[NS];
   C w[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    nb[s] = ld_uniform(nbp + s);
-    w[s] = ld_uniform(wp + s);
+    off[s] = (uint32_t)nbp[s] * L;
+    w[s] = wp[s];
   }
-  for (int k0 = 0; k0 < a.L; k0 += 64) {
-    const int k = k0 + lane;
-    if (k < a.L) elem_lap<S, NS>(static_cast<const S*>(a.in), static_cast<S*>(a.out), a.L, node, k, nb, w);
-  }
-}
-
-template <class S, int OP>
-__device__ __forceinline__ void slab_node(const Args& a, int64_t node, int lane) {
-  if constexpr (OP == OP_LAP) {
-    // two-ring sizes on O-grids are 14..22; entries past the count are padding
-    // (the node itself, weight 0), so a larger instance stays exact
-    const int cnt = ld_uniform(a.nbr + node * a.stride + a.stride - 1);
-    if (cnt == 18) slab_lap<S, 18>(a, node, lane);
-    else if (cnt <= 16) slab_lap<S, 16>(a, node, lane);
-    else if (cnt == 17) slab_lap<S, 17>(a, node, lane);
-    else if (cnt <= 20) slab_lap<S, 20>(a, node, lane);
-    else slab_lap<S, kLapMax - 1>(a, node, lane);
-  } else {
-    const int deg = ld_uniform(a.nbr + node * 8 + 7);
-    if (deg == 6) slab_1ring<S, OP, 6>(a, node, lane);
-    else if (deg == 5) slab_1ring<S, OP, 5>(a, node, lane);
-    else slab_1ring<S, OP, 7>(a, node, lane);   // degree 7, or padding for degrees < 5
-  }
-}
-
-// ---- several nodes per wave (columns of at most 32 levels) ------------------
-//
-// Lanes belong to different nodes, so every lane reads its own table row and
-// uses the full padded width (padding adds exact zeros).
-
-template <class S, int OP>
-__device__ __forceinline__ void packed_elem(const Args& a, int64_t node, int k) {
-  using C = typename Traits<S>::C;
-  using C2 = typename Traits<S>::C2;
-  if constexpr (OP == OP_LAP) {
-    const int32_t* nbp = a.nbr + node * a.stride;
-    const C* wp = static_cast<const C*>(a.coef) + node * a.stride;
-    int nb[kLapMax - 1];
-    C w[kLapMax - 1];
+  const uint32_t self = (uint32_t)nd * L;
+  const S* __restrict__ in = static_cast<const S*>(a.in);
+  S* __restrict__ out = static_cast<S*>(a.out);
+  const int P = a.P;
+  const int nsl = (a.L + P - 1) / P;
+  for (int r0 = 0; r0 < nsl; r0 += U) {
+    uint32_t kc[U];
+    bool st[U];
 #pragma unroll
-    for (int s = 0; s < kLapMax - 1; ++s) {
-      nb[s] = nbp[s];
-      w[s] = wp[s];
+    for (int u = 0; u < U; ++u) {
+      const uint32_t k = (uint32_t)(t + P * (r0 + u));
+      st[u] = ok && k < L;
+      kc[u] = k < L ? k : L - 1;
     }
-    elem_lap<S, kLapMax - 1>(static_cast<const S*>(a.in), static_cast<S*>(a.out), a.L, node, k, nb, w);
-  } else {
-    const int32_t* nbp = a.nbr + node * 8;
-    const C2* cfp = static_cast<const C2*>(a.coef) + node * 8;
-    int nb[7];
-    C2 cf[7];
+    C v[U][NS], x0[U];
 #pragma unroll
-    for (int s = 0; s < 7; ++s) {
-      nb[s] = nbp[s];
-      cf[s] = cfp[s];
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = ld1(in + (size_t)(off[s] + kc[u]));
+      x0[u] = ld1(in + (size_t)(self + kc[u]));
     }
-    elem_1ring<S, OP, 7>(a, node, k, nb, cf, cfp[7]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      C acc = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc = fma(w[s], v[u][s] - x0[u], acc);
+      if (st[u]) st1(out + (size_t)(self + kc[u]), acc);
+    }
   }
 }
 
-// Work of logical block `lb`: waves_per_block * npw nodes (or node groups).
-template <class S, int OP>
+// gbase: first position (in the node order) of the wave's group of G nodes.
+template <class S, int OP, int U>
+__device__ __forceinline__ void run_group(const Args& a, int64_t gbase, int lane) {
+  const int P = a.P;
+  const int G = 64 / P;
+  const int j = lane / P;
+  const int t = lane - j * P;
+  const int64_t q = gbase + j;
+  const bool ok = j < G && q < a.V;
+  const int64_t nd = a.order[ok ? q : gbase];   // gbase < V: a valid node for idle lanes
+  // The padded wide variants serve the few waves that touch a node of
+  // degree 5 or 7 (16 + 4 per mesh) or a wide two-ring; they run one slice
+  // per iteration so that they do not set the register budget of the kernel.
+  if constexpr (OP == OP_LAP) {
+    const int cnt = a.nbr[nd * kLapStride + kLapStride - 1];
+    if (__all(cnt <= 18)) run_lap<S, 18, U>(a, nd, ok, t);
+    else run_lap<S, kLapStride - 1, 1>(a, nd, ok, t);
+  } else {
+    const int deg = a.nbr[nd * 8 + 7];
+    if (__all(deg == 6)) run_1ring<S, OP, 6, U>(a, nd, ok, t);
+    else run_1ring<S, OP, 7, 1>(a, nd, ok, t);
+  }
+}
+
+// Work of logical block `lb`: waves_per_block * npw node groups.
+template <class S, int OP, int U>
 __device__ __forceinline__ void process_block(const Args& a, int64_t lb) {
   const int wpb = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (a.pack == 0) {
-    const int64_t base = lb * (int64_t)wpb * a.npw;
-    for (int r = 0; r < a.npw; ++r) {
-      const int64_t node = base + (int64_t)r * wpb + wave;
-      if (node >= a.V) break;
-      slab_node<S, OP>(a, node, lane);
-    }
-  } else {
-    const int sub = lane / a.L;
-    const int k = lane - sub * a.L;
-    for (int r = 0; r < a.npw; ++r) {
-      const int64_t group = (lb * a.npw + r) * wpb + wave;
-      const int64_t node = group * a.pack + sub;
-      if (sub < a.pack && node < a.V) packed_elem<S, OP>(a, node, k);
-    }
+  const int G = 64 / a.P;
+  for (int r = 0; r < a.npw; ++r) {
+    const int64_t gbase = ((lb * a.npw + r) * wpb + wave) * G;
+    if (gbase >= a.V) break;
+    run_group<S, OP, U>(a, gbase, lane);
   }
 }
 
@@ -321,17 +282,17 @@ __device__ __forceinline__ int64_t logical_block(int64_t b, int64_t nblocks, int
   return (b & 7) * per + (b >> 3);
 }
 
-template <class S, int OP>
-__global__ __launch_bounds__(1024) void k_op(Args a, int64_t nblocks, int remap) {
+template <class S, int OP, int U>
+__global__ __launch_bounds__(256) void k_op(Args a, int64_t nblocks, int remap) {
   const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
   if (lb >= nblocks) return;
-  process_block<S, OP>(a, lb);
+  process_block<S, OP, U>(a, lb);
 }
 
 // Persistent batched form: the global tile index space is the concatenation
 // of each tracer's blocks; every workgroup walks a contiguous range of it.
 template <class S, int OP>
-__global__ __launch_bounds__(1024) void k_batched(Args base, const BatchItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(256) void k_batched(Args base, const BatchItem* __restrict__ items, int nitems,
                                                   int64_t total, int remap) {
   const int64_t nb = gridDim.x;
   const int64_t lb = logical_block(blockIdx.x, nb, remap);   // grid is a multiple of 8 when remapping
@@ -340,47 +301,79 @@ __global__ __launch_bounds__(1024) void k_batched(Args base, const BatchItem* __
   const int64_t t1 = t0 + per < total ? t0 + per : total;
   int item = 0;
   for (int64_t tile = t0; tile < t1; ++tile) {
+    // tiles ascend, so the item index only moves forward
     while (item + 1 < nitems && items[item + 1].tile_begin <= tile) ++item;
-    // tiles are ascending, so the search from the first item only moves forward
     Args a = base;
     a.in = items[item].in;
     a.out = items[item].out;
     a.L = items[item].nlev;
-    a.pack = items[item].pack;
-    process_block<S, OP>(a, tile - items[item].tile_begin);
+    a.P = items[item].lanes;
+    const int64_t lb2 = tile - items[item].tile_begin;
+    switch (items[item].unroll) {
+      case 1: process_block<S, OP, 1>(a, lb2); break;
+      case 2: process_block<S, OP, 2>(a, lb2); break;
+      default: process_block<S, OP, 3>(a, lb2); break;
+    }
   }
 }
 
-// ---- conservation: fixed-order FP64 sums of V_i div_ik -------------------------
+// ---- conservation: fixed-order FP64 sums of V_i div_ik --------------------------
+//
+// Workgroup b reduces nodes [b*chunk, (b+1)*chunk) for every level.  Wave w
+// takes nodes w, w + W, ... of the chunk and reads each node's column in one
+// go (lane = level within a 256-level block, four 64-level slices), so every
+// column is fetched once; waves are then combined in order through LDS and a
+// second pass sums the workgroup partials in order.  Deterministic by
+// construction.
 
 constexpr int kConsWaves = 4;
+constexpr int kConsBlockLevels = 256;
 
 template <class S>
-__global__ __launch_bounds__(256) void k_cons_partial(const S* __restrict__ div, const double* __restrict__ vol,
-                                                      int64_t V, int L, int64_t chunk, double* __restrict__ part) {
-  __shared__ double red[kConsWaves][64][2];
-  const int wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(64 * kConsWaves) void k_cons_partial(const S* __restrict__ div,
+                                                                  const double* __restrict__ vol, int64_t V,
+                                                                  int L, int64_t chunk, double* __restrict__ part) {
+  __shared__ double red[kConsWaves][kConsBlockLevels][2];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t n0 = (int64_t)blockIdx.x * chunk;
   const int64_t n1 = n0 + chunk < V ? n0 + chunk : V;
-  for (int k0 = 0; k0 < L; k0 += 64) {
-    const int k = k0 + lane;
-    double s = 0.0, ab = 0.0;
-    if (k < L) {
-      for (int64_t i = n0 + wave; i < n1; i += kConsWaves) {
-        const double p = vol[i] * (double)ld1(div + i * (int64_t)L + k);
-        s += p;
-        ab += fabs(p);
+  for (int kb = 0; kb < L; kb += kConsBlockLevels) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0}, ab[4] = {0.0, 0.0, 0.0, 0.0};
+    bool in[4];
+    int kc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = kb + lane + 64 * r;
+      in[r] = k < L;
+      kc[r] = k < L ? k : L - 1;
+    }
+    for (int64_t i = n0 + wave; i < n1; i += kConsWaves) {
+      const double v = vol[i];
+      const S* col = div + i * (int64_t)L;
+      double p[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p[r] = v * (double)ld1(col + kc[r]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (in[r]) {
+          s[r] += p[r];
+          ab[r] += fabs(p[r]);
+        }
       }
     }
-    red[wave][lane][0] = s;
-    red[wave][lane][1] = ab;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[wave][lane + 64 * r][0] = s[r];
+      red[wave][lane + 64 * r][1] = ab[r];
+    }
     __syncthreads();
-    if (wave == 0 && k < L) {
-      double ts = red[0][lane][0], ta = red[0][lane][1];
+    const int k = kb + (int)threadIdx.x;
+    if (threadIdx.x < kConsBlockLevels && k < L) {
+      double ts = red[0][threadIdx.x][0], ta = red[0][threadIdx.x][1];
       for (int w = 1; w < kConsWaves; ++w) {
-        ts += red[w][lane][0];
-        ta += red[w][lane][1];
+        ts += red[w][threadIdx.x][0];
+        ta += red[w][threadIdx.x][1];
       }
       part[((int64_t)blockIdx.x * L + k) * 2] = ts;
       part[((int64_t)blockIdx.x * L + k) * 2 + 1] = ta;
@@ -404,45 +397,48 @@ __global__ void k_cons_final(const double* __restrict__ part, int nparts, int L,
 
 // ---- dispatch ---------------------------------------------------------------
 
-Args make_args(int op, const DevTables& t, int64_t V, int nlev, const void* in, void* out, const Shape& sh) {
+Args make_args(int op, const DevTables& t, const int32_t* order, int64_t V, int nlev, const void* in, void* out,
+               const Shape& sh) {
   Args a;
+  a.order = order;
   if (op == OP_LAP) {
     a.nbr = t.lap_nbr;
     a.coef = t.lap_w;
-    a.stride = t.lap_stride;
   } else {
     a.nbr = t.nbr8;
     a.coef = t.coef[op];
-    a.stride = 8;
   }
   a.in = in;
   a.out = out;
   a.V = V;
   a.L = nlev;
-  a.pack = pack_factor(nlev);
+  a.P = lanes_per_node(nlev, sh);
   a.npw = sh.nodes_per_wave;
   return a;
 }
 
-int64_t blocks_for(int64_t V, int nlev, const Shape& sh) {
-  const int pack = pack_factor(nlev);
-  const int64_t per_block = (int64_t)sh.waves_per_block * sh.nodes_per_wave * (pack ? pack : 1);
-  return (V + per_block - 1) / per_block;
+template <class S, int OP>
+hipError_t launch_u(const Args& a, int U, dim3 g, dim3 b, int64_t nblocks, int remap, hipStream_t st) {
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_op<S, OP, 1>), g, b, 0, st, a, nblocks, remap); break;
+    case 2: hipLaunchKernelGGL((k_op<S, OP, 2>), g, b, 0, st, a, nblocks, remap); break;
+    default: hipLaunchKernelGGL((k_op<S, OP, 3>), g, b, 0, st, a, nblocks, remap); break;
+  }
+  return hipGetLastError();
 }
 
 template <class S>
-hipError_t launch_op_t(int op, const Args& a, int64_t nblocks, const Shape& sh, hipStream_t st) {
+hipError_t launch_op_t(int op, const Args& a, int U, int64_t nblocks, const Shape& sh, hipStream_t st) {
   const int64_t grid = sh.xcd_remap ? (nblocks + 7) / 8 * 8 : nblocks;
   const dim3 g((unsigned)grid), b((unsigned)(64 * sh.waves_per_block));
   switch (op) {
-    case OP_GRAD: hipLaunchKernelGGL((k_op<S, OP_GRAD>), g, b, 0, st, a, nblocks, sh.xcd_remap); break;
-    case OP_DIV: hipLaunchKernelGGL((k_op<S, OP_DIV>), g, b, 0, st, a, nblocks, sh.xcd_remap); break;
-    case OP_GRADT: hipLaunchKernelGGL((k_op<S, OP_GRADT>), g, b, 0, st, a, nblocks, sh.xcd_remap); break;
-    case OP_DIVT: hipLaunchKernelGGL((k_op<S, OP_DIVT>), g, b, 0, st, a, nblocks, sh.xcd_remap); break;
-    case OP_LAP: hipLaunchKernelGGL((k_op<S, OP_LAP>), g, b, 0, st, a, nblocks, sh.xcd_remap); break;
+    case OP_GRAD: return launch_u<S, OP_GRAD>(a, U, g, b, nblocks, sh.xcd_remap, st);
+    case OP_DIV: return launch_u<S, OP_DIV>(a, U, g, b, nblocks, sh.xcd_remap, st);
+    case OP_GRADT: return launch_u<S, OP_GRADT>(a, U, g, b, nblocks, sh.xcd_remap, st);
+    case OP_DIVT: return launch_u<S, OP_DIVT>(a, U, g, b, nblocks, sh.xcd_remap, st);
+    case OP_LAP: return launch_u<S, OP_LAP>(a, U, g, b, nblocks, sh.xcd_remap, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <class S>
@@ -465,41 +461,74 @@ hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int n
 
 }  // namespace
 
-hipError_t launch_op(int op, int dtype, const DevTables& t, int64_t V, int nlev, const void* in, void* out,
-                     const Shape& shape, hipStream_t stream) {
-  if (op == OP_LAP && t.lap_stride != kLapMax) return hipErrorInvalidValue;
-  const Args a = make_args(op, t, V, nlev, in, out, shape);
+int lanes_per_node(int nlev, const Shape& sh) {
+  if (nlev <= 32) return nlev;
+  if (sh.lanes_per_node > 0) return sh.lanes_per_node;
+  // best lane utilisation nlev / (P * ceil(nlev / P)); ties go to the wider P
+  int best = 64;
+  double bu = -1.0;
+  for (int p : {64, 32, 16}) {
+    const int nsl = (nlev + p - 1) / p;
+    const double u = (double)nlev / (double)(p * nsl);
+    if (u > bu + 1e-12) {
+      bu = u;
+      best = p;
+    }
+  }
+  return best;
+}
+
+int slices_per_iter(int nlev, const Shape& sh) {
+  const int P = lanes_per_node(nlev, sh);
+  const int nsl = (nlev + P - 1) / P;
+  int U = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
+  if (U > 3) U = 3;
+  return U < nsl ? U : nsl;
+}
+
+int64_t blocks_for(int64_t V, int nlev, const Shape& sh) {
+  const int G = 64 / lanes_per_node(nlev, sh);
+  const int64_t per_block = (int64_t)sh.waves_per_block * sh.nodes_per_wave * G;
+  return (V + per_block - 1) / per_block;
+}
+
+hipError_t launch_op(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V, int nlev,
+                     const void* in, void* out, const Shape& shape, hipStream_t stream) {
+  if (op == OP_LAP && t.lap_stride != kLapStride) return hipErrorInvalidValue;
+  const Args a = make_args(op, t, order, V, nlev, in, out, shape);
+  const int U = slices_per_iter(nlev, shape);
   const int64_t nblocks = blocks_for(V, nlev, shape);
   switch (dtype) {
-    case DT_F64: return launch_op_t<double>(op, a, nblocks, shape, stream);
-    case DT_F32: return launch_op_t<float>(op, a, nblocks, shape, stream);
-    case DT_BF16: return launch_op_t<bf16_t>(op, a, nblocks, shape, stream);
+    case DT_F64: return launch_op_t<double>(op, a, U, nblocks, shape, stream);
+    case DT_F32: return launch_op_t<float>(op, a, U, nblocks, shape, stream);
+    case DT_BF16: return launch_op_t<bf16_t>(op, a, U, nblocks, shape, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
 int conservation_parts(int64_t V, int nlev) {
   (void)nlev;
-  int64_t p = (V + 255) / 256;
-  return (int)(p < 1024 ? p : 1024);
+  const int64_t p = (V + 63) / 64;
+  return (int)(p < 4096 ? p : 4096);
 }
 
 hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev, const void* div, double* scratch,
                                double* out_sum, double* out_abs, hipStream_t stream) {
   const int parts = conservation_parts(V, nlev);
   const int64_t chunk = (V + parts - 1) / parts;
+  const dim3 g(parts), b(64 * kConsWaves);
   switch (dtype) {
     case DT_F64:
-      hipLaunchKernelGGL(k_cons_partial<double>, dim3(parts), dim3(256), 0, stream,
-                         static_cast<const double*>(div), vol, V, nlev, chunk, scratch);
+      hipLaunchKernelGGL(k_cons_partial<double>, g, b, 0, stream, static_cast<const double*>(div), vol, V, nlev,
+                         chunk, scratch);
       break;
     case DT_F32:
-      hipLaunchKernelGGL(k_cons_partial<float>, dim3(parts), dim3(256), 0, stream,
-                         static_cast<const float*>(div), vol, V, nlev, chunk, scratch);
+      hipLaunchKernelGGL(k_cons_partial<float>, g, b, 0, stream, static_cast<const float*>(div), vol, V, nlev,
+                         chunk, scratch);
       break;
     case DT_BF16:
-      hipLaunchKernelGGL(k_cons_partial<bf16_t>, dim3(parts), dim3(256), 0, stream,
-                         static_cast<const bf16_t*>(div), vol, V, nlev, chunk, scratch);
+      hipLaunchKernelGGL(k_cons_partial<bf16_t>, g, b, 0, stream, static_cast<const bf16_t*>(div), vol, V, nlev,
+                         chunk, scratch);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -512,9 +541,10 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
 
 int64_t tiles_for(int64_t V, int nlev, const Shape& shape) { return blocks_for(V, nlev, shape); }
 
-hipError_t launch_batched(int op, int dtype, const DevTables& t, int64_t V, const BatchItem* items, int nitems,
-                          int64_t total_tiles, const Shape& shape, int num_cus, hipStream_t stream) {
-  Args a = make_args(op, t, V, 1, nullptr, nullptr, shape);
+hipError_t launch_batched(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V,
+                          const BatchItem* items, int nitems, int64_t total_tiles, const Shape& shape, int num_cus,
+                          hipStream_t stream) {
+  Args a = make_args(op, t, order, V, 1, nullptr, nullptr, shape);
   switch (dtype) {
     case DT_F64: return launch_batched_t<double>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
     case DT_F32: return launch_batched_t<float>(op, a, items, nitems, total_tiles, shape, num_cus, stream);

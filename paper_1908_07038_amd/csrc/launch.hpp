@@ -22,18 +22,26 @@ struct DevTables {
 
 struct Shape {
   int waves_per_block = 4;   // 64-lane waves per workgroup
-  int nodes_per_wave = 2;    // nodes (or node groups) per wave per workgroup
+  int nodes_per_wave = 2;    // node groups per wave per workgroup
   int blocks_per_cu = 4;     // persistent kernels only
   int xcd_remap = 1;         // contiguous slices of work per XCD
+  int lanes_per_node = 0;    // 0: chosen from nlev; else 16, 32 or 64 (nlev > 32)
+  int slices_per_iter = 0;   // 0: 3 (capped by the slice count); else 1..3
+  int band_rows = 0;         // 0: kDefaultBandRows; rows per band of the node order
 };
 
-// Number of nodes handled together by one wave: 0 means one node per wave with
-// its levels spread over the lanes (nlev > 32), otherwise floor(64 / nlev)
-// nodes share a wave, one (node, level) per lane.
-inline int pack_factor(int nlev) { return nlev > 32 ? 0 : 64 / nlev; }
+constexpr int kDefaultBandRows = 32;
+inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
 
-// Single-field operator launch; in/out are device pointers of the dtype.
-hipError_t launch_op(int op, int dtype, const DevTables& t, int64_t V, int nlev,
+// Lanes per node: nlev for columns of at most 32 levels (64 / nlev nodes per
+// wave), else the width in {64, 32, 16} that wastes the fewest lanes.
+int lanes_per_node(int nlev, const Shape& sh);
+// Level slices per loop iteration of a lane (1..3).
+int slices_per_iter(int nlev, const Shape& sh);
+
+// Single-field operator launch; in/out are device pointers of the dtype and
+// `order` the device node order (a permutation of 0..V-1) work follows.
+hipError_t launch_op(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V, int nlev,
                      const void* in, void* out, const Shape& shape, hipStream_t stream);
 
 // Conservation sums: partial [nparts][nlev][2] doubles of scratch, then the
@@ -48,11 +56,13 @@ struct BatchItem {
   const void* in;
   void* out;
   int32_t nlev;
-  int32_t pack;          // pack_factor(nlev)
+  int32_t lanes;         // lanes_per_node(nlev)
+  int32_t unroll;        // slices_per_iter(nlev)
+  int32_t reserved;
   int64_t tile_begin;    // first global tile of this tracer
 };
 int64_t tiles_for(int64_t V, int nlev, const Shape& shape);
-hipError_t launch_batched(int op, int dtype, const DevTables& t, int64_t V,
+hipError_t launch_batched(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V,
                           const BatchItem* items, int nitems, int64_t total_tiles,
                           const Shape& shape, int num_cus, hipStream_t stream);
 

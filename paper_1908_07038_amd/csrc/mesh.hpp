@@ -75,4 +75,11 @@ void build_host_mesh(int N, double radius, HostMesh& m);
 // Build the per-node tables from the geometry.
 void build_op_tables(const HostMesh& m, OpTables& t);
 
+// Processing order of the nodes for cache reuse: the rows are cut into bands
+// of `band_rows` rows; within a band, nodes are ordered by longitude (exact
+// rational comparison j/n_k), then by row.  Work walks this order, so the
+// rows above and below a node are visited at the same longitude and stay in
+// cache; only rows at band edges are fetched twice.
+void build_band_order(const HostMesh& m, int band_rows, std::vector<int32_t>& order);
+
 }  // namespace atlasnabla

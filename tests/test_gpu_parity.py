@@ -201,3 +201,46 @@ def test_argument_errors():
     with pytest.raises(ValueError):
         pa.gradient(M, g)
     torch.cuda.synchronize()
+
+
+SHAPES = [dict(lanes_per_node=p, slices_per_iter=u, waves_per_block=w, nodes_per_wave=n, xcd_remap=x,
+               band_rows=h)
+          for (p, u, w, n, x, h) in [(16, 1, 1, 1, 2, 1), (16, 3, 4, 2, 1, 0), (32, 2, 2, 4, 1, 7),
+                                     (64, 3, 4, 8, 2, 64), (64, 1, 1, 3, 1, 1000), (32, 3, 4, 1, 2, 2)]]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_launch_shape_invariance(dtype):
+    """Every tunable launch shape gives the same values (up to the sign of
+    zero) as the default one: the per-element slot order never changes."""
+    M = gpu_mesh(32)
+    codes = {torch.float64: pa.F64, torch.float32: pa.F32, torch.bfloat16: pa.BF16}
+    for L in (137, 91, 40, 19):
+        x = torch.from_numpy(_input(32, L, 1, 21)).to(DEV).to(dtype)
+        w = torch.from_numpy(_input(32, L, 2, 22)).to(DEV).to(dtype)
+        cases = [(pa.OP_GRADIENT, pa.gradient, x), (pa.OP_DIVERGENCE, pa.divergence, w),
+                 (pa.OP_LAPLACIAN, pa.laplacian, x), (pa.OP_GRADIENT_ADJOINT, pa.gradient_adjoint, w),
+                 (pa.OP_DIVERGENCE_ADJOINT, pa.divergence_adjoint, x)]
+        for op, fn, inp in cases:
+            ref = fn(M, inp)
+            for sh in SHAPES:
+                pa.set_tune(M, op, codes[dtype], sh)
+                y = fn(M, inp)
+                torch.cuda.synchronize()
+                assert torch.equal(y, ref), (op, L, sh)
+            pa.set_tune(M, op, codes[dtype], None)
+
+
+def test_tuner_returns_a_valid_shape():
+    M = gpu_mesh(32)
+    x = torch.from_numpy(_input(32, 137, 1, 23)).to(DEV).float()
+    y = torch.empty((M.nnodes, 137, 2), dtype=torch.float32, device=DEV)
+    shape, ms = pa.tune(M, pa.OP_GRADIENT, x, y, reps=2)
+    assert ms > 0 and shape["waves_per_block"] in (1, 2, 4)
+    # the tuner leaves the output of its last candidate, identical to any shape's
+    pa.set_tune(M, pa.OP_GRADIENT, pa.F32, shape)
+    tuned = pa.gradient(M, x)
+    pa.set_tune(M, pa.OP_GRADIENT, pa.F32, None)
+    ref = pa.gradient(M, x)
+    torch.cuda.synchronize()
+    assert torch.equal(tuned, ref) and torch.equal(y, ref)

@@ -1,0 +1,243 @@
+"""Full-size workloads on the GPU, in the launch configuration the benchmark
+times, checked against the oracle on sampled outputs and by identities that
+hold at any size.
+
+* O1280 x 137 (FP64, FP32, BF16 storage): every operator at ~700 sampled
+  nodes (random, polar rows, nodes of degree 5 and 7, row starts, equator).
+* O640 x 137 adjoints (FP64, FP32): autograd backward of sum(w * grad f) and
+  of sum(w' * div uv), dot-product tests, central differences on 100 seeded
+  node-level entries, sampled oracle values of the adjoints.
+* O640 batched: 64 tracers with level counts drawn from {1, 19, 60, 91, 137},
+  one persistent launch per operator replayed as a HIP graph, bitwise equal
+  to the single-field calls and sampled against the oracle.
+Bars as in test_gpu_parity (FP64 1e-12, FP32 1e-5 total, BF16 4e-3 kernel).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1908_07038_amd as pa
+import workloads as W
+from oracle import nabla
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+DEV = torch.device("cuda", 0)
+R = 6371220.0
+_CACHE = {}
+
+
+def oracle_mesh(N):
+    if N not in _CACHE:
+        m = oracle.build_mesh(N)
+        _CACHE[N] = (m, oracle.build_dual(m, R))
+    return _CACHE[N]
+
+
+def sample_nodes(m, count, seed):
+    g = m.grid
+    rng = np.random.default_rng(seed)
+    special = [np.arange(g.row_off[0], g.row_off[2]),                      # polar rows
+               np.arange(g.row_off[g.nrows - 2], g.row_off[g.nrows]),
+               np.nonzero(m.degree != 6)[0],                              # degree 5 and 7
+               g.row_off[:-1][::max(1, g.nrows // 64)],                   # row starts
+               g.row_off[g.N - 1] + np.arange(0, g.row_size[g.N - 1], 97),
+               rng.choice(m.nnodes, count, replace=False)]
+    return np.unique(np.concatenate(special)).astype(np.int64)
+
+
+def rows(t, idx):
+    """Rows idx of a device tensor as an FP64 numpy array (input data)."""
+    return t[torch.from_numpy(np.asarray(idx)).to(t.device)].double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_o1280_sampled_parity():
+    print("O1280 x 137: building meshes", flush=True)
+    M = pa.Mesh("O1280", radius=R, device=0)
+    m, g = oracle_mesh(1280)
+    L = 137
+    co = M.coords()
+    s, trend = W.workload_o1280(co, nlev=L, device=DEV)
+    tr = torch.from_numpy(trend).to(DEV)
+    f64 = (s[:, None] + tr[None, :]).contiguous()
+    su = W.sh_field(co, 128, 1013, device=DEV)
+    sv = W.sh_field(co, 128, 1023, device=DEV)
+    uv64 = torch.stack([su[:, None] + tr[None, :], sv[:, None] - tr[None, :]], dim=2).contiguous()
+    del s, su, sv
+    nodes = sample_nodes(m, 600, 77)
+    ops = [("gradient", pa.gradient, nabla.gradient_at, "f"),
+           ("divergence", pa.divergence, nabla.divergence_at, "uv"),
+           ("laplacian", pa.laplacian, nabla.laplacian_at, "f"),
+           ("gradient_adjoint", pa.gradient_adjoint, nabla.gradient_adjoint_at, "uv"),
+           ("divergence_adjoint", pa.divergence_adjoint, nabla.divergence_adjoint_at, "f")]
+    refs = {}
+    for name, _, ora, inp in ops:
+        src = f64 if inp == "f" else uv64
+        n_, refs[name] = ora(m, g, lambda idx, src=src: rows(src, idx), nodes)
+        assert np.array_equal(n_, nodes)
+    for dt, tol in [(torch.float64, 1e-12), (torch.float32, 1e-5), (torch.bfloat16, 4e-3)]:
+        f = f64.to(dt)
+        uv = uv64.to(dt)
+        for name, fn, ora, inp in ops:
+            x = f if inp == "f" else uv
+            y = fn(M, x)
+            torch.cuda.synchronize()
+            got = rows(y, nodes)
+            if dt == torch.bfloat16:
+                _, ref = ora(m, g, lambda idx, x=x: rows(x, idx), nodes)   # kernel-only error
+                total = rel(got, refs[name])
+            else:
+                ref = refs[name]
+                total = rel(got, ref)
+            err = rel(got, ref)
+            print(f"  {name} {dt}: rel L2 {err:.3e} (total vs FP64 input {total:.3e})", flush=True)
+            assert err <= tol, (name, dt, err)
+            del y
+        del f, uv
+        torch.cuda.empty_cache()
+    # invariants at full size
+    f = f64.float()
+    gc = pa.gradient(M, torch.full_like(f, 2.5))
+    assert torch.count_nonzero(gc).item() == 0
+    d = pa.divergence(M, uv64.float())
+    cs, ca = pa.conservation(M, d)
+    assert (cs.abs() / ca).max().item() < 1e-6
+    d64 = pa.divergence(M, uv64)
+    cs, ca = pa.conservation(M, d64)
+    assert (cs.abs() / ca).max().item() < 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_o640_adjoints(dtype):
+    print(f"O640 x 137 adjoints {dtype}", flush=True)
+    M = pa.Mesh("O640", radius=R, device=0)
+    m, g = oracle_mesh(640)
+    V, L = M.nnodes, 137
+    co = M.coords()
+    s = W.sh_field(co, 64, 1004, device=DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(1004)
+    f = (s[:, None] * (1.0 + 0.1 * torch.arange(L, device=DEV, dtype=torch.float64))[None, :]
+         + 1e-3 * torch.randn((V, L), generator=gen, device=DEV, dtype=torch.float64)).to(dtype)
+    gen.manual_seed(1014)
+    w = torch.randn((V, L, 2), generator=gen, device=DEV, dtype=torch.float64).to(dtype)
+    fr = f.clone().requires_grad_(True)
+    loss = (w * pa.grad(M, fr)).sum()
+    loss.backward()
+    fbar = fr.grad
+    assert torch.equal(fbar, pa.gradient_adjoint(M, w))
+    # divergence: backward of sum(w' * div uv)
+    gen.manual_seed(1044)
+    uv = torch.randn((V, L, 2), generator=gen, device=DEV, dtype=torch.float64).to(dtype).requires_grad_(True)
+    gen.manual_seed(1054)
+    wd = torch.randn((V, L), generator=gen, device=DEV, dtype=torch.float64).to(dtype)
+    (wd * pa.div(M, uv)).sum().backward()
+    assert torch.equal(uv.grad, pa.divergence_adjoint(M, wd))
+    # oracle values of both adjoints at sampled nodes
+    nodes = sample_nodes(m, 400, 78)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    _, ref = nabla.gradient_adjoint_at(m, g, lambda idx: rows(w, idx), nodes)
+    assert rel(rows(fbar, nodes), ref) <= tol
+    _, ref = nabla.divergence_adjoint_at(m, g, lambda idx: rows(wd, idx), nodes)
+    assert rel(rows(uv.grad, nodes), ref) <= tol
+    # dot-product tests on random x, y
+    gen.manual_seed(1024)
+    x = torch.randn((V, L), generator=gen, device=DEV, dtype=torch.float64).to(dtype)
+    y = torch.randn((V, L, 2), generator=gen, device=DEV, dtype=torch.float64).to(dtype)
+    dtol = 1e-13 if dtype == torch.float64 else 1e-5
+    lhs = (pa.gradient(M, x).double() * y.double()).sum().item()
+    rhs = (x.double() * pa.gradient_adjoint(M, y).double()).sum().item()
+    assert abs(lhs - rhs) <= dtol * abs(lhs), (lhs, rhs)
+    lhs = (pa.divergence(M, y).double() * x.double()).sum().item()
+    rhs = (y.double() * pa.divergence_adjoint(M, x).double()).sum().item()
+    assert abs(lhs - rhs) <= dtol * abs(lhs), (lhs, rhs)
+    # central differences of the linear loss on 100 seeded entries: only the
+    # stencil of the entry changes, so the difference of the two outputs is
+    # exactly zero elsewhere and the FP64 sum has no cancellation
+    entries = W.fd_entries(V, L, 100, 1034)
+    fd_tol = 1e-9 if dtype == torch.float64 else 1e-4
+    wd64 = w.double()
+    for i, k in entries:
+        fik = f[i, k].item()
+        eps = (1e-3 if dtype == torch.float64 else 0.5) * max(1.0, abs(fik))
+        fp, fm = f.clone(), f.clone()
+        fp[i, k] += eps
+        fm[i, k] -= eps
+        h = (fp[i, k].double() - fm[i, k].double()).item()    # the step actually taken
+        diff = (pa.gradient(M, fp).double() - pa.gradient(M, fm).double())
+        fd = (wd64 * diff).sum().item() / h
+        an = fbar[i, k].double().item()
+        assert abs(fd - an) <= fd_tol * max(abs(an), 1e-30) + 1e-30, (i, k, fd, an)
+
+
+def test_o640_batched_config():
+    print("O640 batched, 64 tracers", flush=True)
+    M = pa.Mesh("O640", radius=R, device=0)
+    m, g = oracle_mesh(640)
+    V = M.nnodes
+    levels = [int(x) for x in W.batch_levels(64, 1005)]
+    need = sum(levels) * V * 4 * 7 + (1 << 31)
+    free, _ = torch.cuda.mem_get_info(DEV)
+    if free < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of device memory, {free / 1e9:.0f} GB free")
+    co = M.coords()
+    tracers = []
+    for t, L in enumerate(levels):
+        s = W.tracer_surface(co, t, device=DEV)
+        scale = 1.0 + torch.arange(L, device=DEV, dtype=torch.float64) / L
+        f = (s[:, None] * scale[None, :]).float().contiguous()
+        gbuf = torch.empty((V, L, 2), device=DEV)
+        d = torch.empty((V, L), device=DEV)
+        fT = torch.empty((V, L), device=DEV)
+        gT = torch.empty((V, L, 2), device=DEV)
+        tracers.append({"gradient": (f, gbuf), "divergence": (gbuf, d), "gradient_adjoint": (gbuf, fT),
+                        "divergence_adjoint": (d, gT)})
+    plan = pa.Batch(M, tracers)
+    for rep in range(2):
+        for tr in tracers:
+            for n in ("divergence", "gradient_adjoint", "divergence_adjoint"):
+                tr[n][1].fill_(float("nan"))
+        plan.graph_launch()
+        torch.cuda.synchronize()
+    # bitwise against the single-field chain
+    for tr in tracers:
+        f = tr["gradient"][0]
+        g1 = pa.gradient(M, f)
+        d1 = pa.divergence(M, g1)
+        assert torch.equal(tr["gradient"][1], g1)
+        assert torch.equal(tr["divergence"][1], d1)
+        assert torch.equal(tr["gradient_adjoint"][1], pa.gradient_adjoint(M, g1))
+        assert torch.equal(tr["divergence_adjoint"][1], pa.divergence_adjoint(M, d1))
+        del g1, d1
+    # oracle at sampled nodes for a tracer of each level count (FP64 chain)
+    nodes = sample_nodes(m, 150, 79)
+    seen = set()
+    for t, L in enumerate(levels):
+        if L in seen:
+            continue
+        seen.add(L)
+        tr = tracers[t]
+        get_f = lambda idx, x=tr["gradient"][0]: rows(x, idx)   # noqa: E731
+        _, rg = nabla.gradient_at(m, g, get_f, nodes)
+        _, rl = nabla.laplacian_at(m, g, get_f, nodes)
+        assert rel(rows(tr["gradient"][1], nodes), rg) <= 1e-5
+        assert rel(rows(tr["divergence"][1], nodes), rl) <= 1e-5
+        # adjoints of the chain: grad^T(grad f) and div^T(div grad f)
+        ring_nodes, ring_eids = nabla._incident(m, nodes)
+        ring = np.unique(np.concatenate([ring_nodes, m.edges[ring_eids].ravel()]))
+        ring, g_ring = nabla.gradient_at(m, g, get_f, ring)
+        lut = np.full(m.nnodes, -1)
+        lut[ring] = np.arange(ring.size)
+        _, rgt = nabla.gradient_adjoint_at(m, g, lambda idx: g_ring[lut[idx]], nodes)
+        assert rel(rows(tr["gradient_adjoint"][1], nodes), rgt) <= 1e-5
+        ring, l_ring = nabla.laplacian_at(m, g, get_f, ring)
+        _, rdt = nabla.divergence_adjoint_at(m, g, lambda idx: l_ring[lut[idx]], nodes)
+        assert rel(rows(tr["divergence_adjoint"][1], nodes), rdt) <= 1e-5
+    assert math.isfinite(float(tracers[0]["divergence_adjoint"][1].abs().max()))
