@@ -39,9 +39,9 @@ OP_ELEMS = {"gradient": (1, 2), "divergence": (2, 1), "laplacian": (1, 1),
             "gradient_adjoint": (2, 1), "divergence_adjoint": (1, 2), "conservation": (1, 0)}
 OP_SWEEPS = {"gradient": 1, "divergence": 1, "laplacian": 2, "gradient_adjoint": 1,
              "divergence_adjoint": 1, "conservation": 0}
-KERNEL_NAME = {"gradient": "k_op<float, 0>", "divergence": "k_op<float, 1>",
-               "gradient_adjoint": "k_op<float, 2>", "divergence_adjoint": "k_op<float, 3>",
-               "laplacian": "k_op<float, 4>", "conservation": "k_cons_partial<float> + k_cons_final"}
+KERNEL_NAME = {"gradient": "k_op<float, 0, U>", "divergence": "k_op<float, 1, U>",
+               "gradient_adjoint": "k_op<float, 2, U>", "divergence_adjoint": "k_op<float, 3, U>",
+               "laplacian": "k_op<float, 4, U>", "conservation": "k_cons_partial<float> + k_cons_final"}
 
 
 def log(*a):
@@ -203,6 +203,8 @@ def main():
     ap.add_argument("--levels", type=int, default=137)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
@@ -210,6 +212,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 30, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     mesh, res = run_gpu(args)
     V, E, L = mesh.nnodes, mesh.nedges, args.levels
     f32 = res["f32"]

@@ -210,8 +210,11 @@ typedef struct {
                                columns of <= 32 levels always use nlev lanes */
   int32_t slices_per_iter;  /* level slices in flight per lane, 1..3         */
   int32_t band_rows;        /* rows per band of the node processing order:
-                               nodes of a band are visited by longitude so
+                               runs of a band are visited by longitude so
                                rows above and below stay in cache            */
+  int32_t run_nodes;        /* consecutive nodes of a row per run             */
+  int32_t nt_stores;        /* 1: non-temporal output stores, 2: plain (the
+                               default)                                      */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;

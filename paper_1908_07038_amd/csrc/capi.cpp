@@ -71,7 +71,7 @@ struct atlas_mesh_s {
   size_t scratch_bytes = 0;
   Shape shape[OP_COUNT][3];
   std::mutex order_mu;
-  std::map<int, const int32_t*> orders;   // band rows -> device node order
+  std::map<std::pair<int, int>, const int32_t*> orders;   // (band rows, run) -> device node order
 
   ~atlas_mesh_s() {
     if (device >= 0) {
@@ -97,15 +97,16 @@ struct atlas_mesh_s {
 
   const DevTables& tables(int dtype) const { return dtype == ATLAS_F64 ? tab64 : tab32; }
 
-  // Device node order for a band height, built and uploaded on first use.
-  const int32_t* order(int band_rows) {
+  // Device node order for a launch shape, built and uploaded on first use.
+  const int32_t* order(const Shape& sh) {
+    const std::pair<int, int> key(band_rows_of(sh), run_nodes_of(sh));
     std::lock_guard<std::mutex> lk(order_mu);
-    auto it = orders.find(band_rows);
+    auto it = orders.find(key);
     if (it != orders.end()) return it->second;
     std::vector<int32_t> ord;
-    build_band_order(host, band_rows, ord);
+    build_band_order(host, key.first, key.second, ord);
     const int32_t* d = upload(ord);
-    orders[band_rows] = d;
+    orders[key] = d;
     return d;
   }
 };
@@ -178,6 +179,8 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->lanes_per_node = s.lanes_per_node;
   t->slices_per_iter = s.slices_per_iter;
   t->band_rows = s.band_rows;
+  t->run_nodes = s.run_nodes;
+  t->nt_stores = s.nt_stores;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -204,6 +207,10 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.slices_per_iter = t->slices_per_iter;
   if (t->band_rows < 0 || t->band_rows > 65536) return fail(ATLAS_EINVAL, "band_rows must be 0..65536");
   s.band_rows = t->band_rows;
+  if (t->run_nodes < 0 || t->run_nodes > 65536) return fail(ATLAS_EINVAL, "run_nodes must be 0..65536");
+  s.run_nodes = t->run_nodes;
+  if (t->nt_stores < 0 || t->nt_stores > 2) return fail(ATLAS_EINVAL, "nt_stores must be 0, 1 or 2");
+  s.nt_stores = t->nt_stores;
   return ATLAS_OK;
 }
 
@@ -227,7 +234,7 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   const Shape& sh = shape_override ? *shape_override : mesh->shape[op][dtype];
   const int32_t* order = nullptr;
   try {
-    order = mesh->order(band_rows_of(sh));
+    order = mesh->order(sh);
   } catch (const std::bad_alloc&) {
     return fail(ATLAS_ENOMEM, "cannot allocate the node order");
   } catch (const std::exception& ex) {
@@ -515,15 +522,20 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
           if ((rc = time_shape(s))) goto done;
         }
   }
-  // stage 3: band height of the node order
+  // stage 3: node order (band height, run length) and store kind
   {
     const Shape base = bs;
-    const int hs[] = {8, 16, 64, 128};
-    for (int h : hs) {
-      Shape s = base;
-      s.band_rows = h;
-      if ((rc = time_shape(s))) goto done;
-    }
+    const int hs[] = {8, 16, 32, 64};
+    const int rs[] = {4, 16, 64};
+    for (int h : hs)
+      for (int r : rs)
+        for (int nt = 1; nt <= 2; ++nt) {
+          Shape s = base;
+          s.band_rows = h;
+          s.run_nodes = r;
+          s.nt_stores = nt;
+          if ((rc = time_shape(s))) goto done;
+        }
   }
   shape_out(bs, best);
   if (best_ms) *best_ms = bestt;
@@ -572,7 +584,7 @@ namespace {
 int plan_upload(atlas_batch_s* b) {
   const int64_t V = b->mesh->host.V;
   try {
-    b->order = b->mesh->order(band_rows_of(b->shape));
+    b->order = b->mesh->order(b->shape);
   } catch (const std::bad_alloc&) {
     return fail(ATLAS_ENOMEM, "cannot allocate the node order");
   } catch (const std::exception& ex) {

@@ -67,25 +67,36 @@ __device__ __forceinline__ float2 ld2(const bf16_t* p) {
   return make_float2(bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16));
 }
 
-// Outputs are written once and not read again by the kernel: non-temporal
-// stores keep them from displacing the neighbour rows held in L2.
+// Output stores: plain, or non-temporal (streamed past L2) when the launch
+// asks for it.  Plain stores let L2 merge the partial cache lines shared by
+// the columns of neighbouring nodes.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void st1(double* p, double v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void st1(float* p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void st1(bf16_t* p, float v) {
-  __builtin_nontemporal_store((bf16_t)f32_to_bf16(v), p);
+template <bool NT, class T>
+__device__ __forceinline__ void st_raw(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
+template <bool NT>
+__device__ __forceinline__ void st1(double* p, double v) { st_raw<NT>(p, v); }
+template <bool NT>
+__device__ __forceinline__ void st1(float* p, float v) { st_raw<NT>(p, v); }
+template <bool NT>
+__device__ __forceinline__ void st1(bf16_t* p, float v) { st_raw<NT>(p, (bf16_t)f32_to_bf16(v)); }
+
+template <bool NT>
 __device__ __forceinline__ void st2(double* p, double x, double y) {
-  __builtin_nontemporal_store(f64x2{x, y}, reinterpret_cast<f64x2*>(p));
+  st_raw<NT>(reinterpret_cast<f64x2*>(p), f64x2{x, y});
 }
+template <bool NT>
 __device__ __forceinline__ void st2(float* p, float x, float y) {
-  __builtin_nontemporal_store(f32x2{x, y}, reinterpret_cast<f32x2*>(p));
+  st_raw<NT>(reinterpret_cast<f32x2*>(p), f32x2{x, y});
 }
+template <bool NT>
 __device__ __forceinline__ void st2(bf16_t* p, float x, float y) {
-  __builtin_nontemporal_store(f32_to_bf16(x) | (f32_to_bf16(y) << 16), reinterpret_cast<uint32_t*>(p));
+  st_raw<NT>(reinterpret_cast<uint32_t*>(p), f32_to_bf16(x) | (f32_to_bf16(y) << 16));
 }
 
 struct Args {
@@ -98,6 +109,7 @@ struct Args {
   int32_t L;            // levels
   int32_t P;            // lanes per node (64 / P nodes per wave)
   int32_t npw;          // node groups per wave per workgroup
+  int32_t nt;           // non-temporal output stores
 };
 
 // ---- one node group per wave --------------------------------------------------
@@ -167,7 +179,10 @@ __device__ __forceinline__ void run_1ring(const Args& a, int64_t nd, bool ok, in
             ay = fma(cf[s].y, v[u][s], ay);
           }
         }
-        if (st[u]) st2(out + 2 * (size_t)(self + kc[u]), ax, ay);
+        if (st[u]) {
+          if (a.nt) st2<true>(out + 2 * (size_t)(self + kc[u]), ax, ay);
+          else st2<false>(out + 2 * (size_t)(self + kc[u]), ax, ay);
+        }
       }
     } else {
       // divergence and gradient adjoint: diag . in_i + sum_s (x, y)_s . in_n
@@ -187,7 +202,10 @@ __device__ __forceinline__ void run_1ring(const Args& a, int64_t nd, bool ok, in
           acc = fma(cf[s].x, v[u][s].x, acc);
           acc = fma(cf[s].y, v[u][s].y, acc);
         }
-        if (st[u]) st1(out + (size_t)(self + kc[u]), acc);
+        if (st[u]) {
+          if (a.nt) st1<true>(out + (size_t)(self + kc[u]), acc);
+          else st1<false>(out + (size_t)(self + kc[u]), acc);
+        }
       }
     }
   }
@@ -233,7 +251,10 @@ __device__ __forceinline__ void run_lap(const Args& a, int64_t nd, bool ok, int 
       C acc = 0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) acc = fma(w[s], v[u][s] - x0[u], acc);
-      if (st[u]) st1(out + (size_t)(self + kc[u]), acc);
+      if (st[u]) {
+        if (a.nt) st1<true>(out + (size_t)(self + kc[u]), acc);
+        else st1<false>(out + (size_t)(self + kc[u]), acc);
+      }
     }
   }
 }
@@ -414,6 +435,7 @@ Args make_args(int op, const DevTables& t, const int32_t* order, int64_t V, int 
   a.L = nlev;
   a.P = lanes_per_node(nlev, sh);
   a.npw = sh.nodes_per_wave;
+  a.nt = nt_of(sh) ? 1 : 0;
   return a;
 }
 

@@ -22,16 +22,21 @@ struct DevTables {
 
 struct Shape {
   int waves_per_block = 4;   // 64-lane waves per workgroup
-  int nodes_per_wave = 2;    // node groups per wave per workgroup
+  int nodes_per_wave = 1;    // node groups per wave per workgroup
   int blocks_per_cu = 4;     // persistent kernels only
   int xcd_remap = 1;         // contiguous slices of work per XCD
   int lanes_per_node = 0;    // 0: chosen from nlev; else 16, 32 or 64 (nlev > 32)
   int slices_per_iter = 0;   // 0: 3 (capped by the slice count); else 1..3
   int band_rows = 0;         // 0: kDefaultBandRows; rows per band of the node order
+  int run_nodes = 0;         // 0: kDefaultRunNodes; consecutive nodes per run of the order
+  int nt_stores = 0;         // 0: default (off), 1: non-temporal output stores, 2: off
 };
 
 constexpr int kDefaultBandRows = 32;
+constexpr int kDefaultRunNodes = 16;
 inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
+inline int run_nodes_of(const Shape& s) { return s.run_nodes > 0 ? s.run_nodes : kDefaultRunNodes; }
+inline bool nt_of(const Shape& s) { return s.nt_stores == 1; }
 
 // Lanes per node: nlev for columns of at most 32 levels (64 / nlev nodes per
 // wave), else the width in {64, 32, 16} that wastes the fewest lanes.

@@ -76,10 +76,12 @@ void build_host_mesh(int N, double radius, HostMesh& m);
 void build_op_tables(const HostMesh& m, OpTables& t);
 
 // Processing order of the nodes for cache reuse: the rows are cut into bands
-// of `band_rows` rows; within a band, nodes are ordered by longitude (exact
-// rational comparison j/n_k), then by row.  Work walks this order, so the
-// rows above and below a node are visited at the same longitude and stay in
-// cache; only rows at band edges are fetched twice.
-void build_band_order(const HostMesh& m, int band_rows, std::vector<int32_t>& order);
+// of `band_rows` rows and each row into runs of `run_nodes` consecutive
+// nodes; within a band, runs are ordered by the longitude of their first node
+// (exact rational comparison j/n_k), then by row.  Work walks this order, so
+// the rows above and below a node are visited at the same longitude and stay
+// in cache (only rows at band edges are fetched twice), while the nodes of a
+// run, whose columns share cache lines, are processed together.
+void build_band_order(const HostMesh& m, int band_rows, int run_nodes, std::vector<int32_t>& order);
 
 }  // namespace atlasnabla

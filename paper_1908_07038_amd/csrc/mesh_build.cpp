@@ -504,22 +504,25 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
   }
 }
 
-void build_band_order(const HostMesh& m, int band_rows, std::vector<int32_t>& order) {
-  if (band_rows < 1) throw std::runtime_error("band_rows must be >= 1");
+void build_band_order(const HostMesh& m, int band_rows, int run_nodes, std::vector<int32_t>& order) {
+  if (band_rows < 1 || run_nodes < 1) throw std::runtime_error("band_rows and run_nodes must be >= 1");
   order.resize(m.V);
-  struct Item { int32_t j, n, row; };
-  std::vector<Item> items;
+  struct Run { int32_t j, n, row; };
+  std::vector<Run> runs;
   int64_t pos = 0;
   for (int k0 = 0; k0 < m.nrows; k0 += band_rows) {
     const int k1 = std::min(m.nrows, k0 + band_rows);
-    items.clear();
+    runs.clear();
     for (int k = k0; k < k1; ++k)
-      for (int j = 0; j < m.row_size[k]; ++j) items.push_back({j, m.row_size[k], k});
-    std::sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
+      for (int j = 0; j < m.row_size[k]; j += run_nodes) runs.push_back({j, m.row_size[k], k});
+    std::sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) {
       const int64_t a = (int64_t)x.j * y.n, b = (int64_t)y.j * x.n;
       return a != b ? a < b : x.row < y.row;
     });
-    for (const Item& it : items) order[pos++] = (int32_t)(m.row_off[it.row] + it.j);
+    for (const Run& r : runs) {
+      const int j1 = std::min(r.n, r.j + run_nodes);
+      for (int j = r.j; j < j1; ++j) order[pos++] = (int32_t)(m.row_off[r.row] + j);
+    }
   }
 }
 
