@@ -403,17 +403,31 @@ __global__ __launch_bounds__(64 * kConsWaves) void k_cons_partial(const S* __res
   }
 }
 
-__global__ void k_cons_final(const double* __restrict__ part, int nparts, int L, double* __restrict__ out_sum,
-                             double* __restrict__ out_abs) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= L) return;
+// One workgroup per level: thread t sums partials t, t + 256, ... in order,
+// then a fixed binary tree combines the 256 thread sums.
+__global__ __launch_bounds__(256) void k_cons_final(const double* __restrict__ part, int nparts, int L,
+                                                    double* __restrict__ out_sum, double* __restrict__ out_abs) {
+  __shared__ double red[256][2];
+  const int k = blockIdx.x;
   double s = 0.0, a = 0.0;
-  for (int p = 0; p < nparts; ++p) {
+  for (int p = threadIdx.x; p < nparts; p += 256) {
     s += part[((int64_t)p * L + k) * 2];
     a += part[((int64_t)p * L + k) * 2 + 1];
   }
-  out_sum[k] = s;
-  out_abs[k] = a;
+  red[threadIdx.x][0] = s;
+  red[threadIdx.x][1] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x][0] += red[threadIdx.x + w][0];
+      red[threadIdx.x][1] += red[threadIdx.x + w][1];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out_sum[k] = red[0][0];
+    out_abs[k] = red[0][1];
+  }
 }
 
 // ---- dispatch ---------------------------------------------------------------
@@ -556,8 +570,7 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cons_final, dim3((nlev + 127) / 128), dim3(128), 0, stream, scratch, parts, nlev, out_sum,
-                     out_abs);
+  hipLaunchKernelGGL(k_cons_final, dim3(nlev), dim3(256), 0, stream, scratch, parts, nlev, out_sum, out_abs);
   return hipGetLastError();
 }
 
