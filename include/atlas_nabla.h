@@ -212,9 +212,14 @@ typedef struct {
   int32_t band_rows;        /* rows per band of the node processing order:
                                runs of a band are visited by longitude so
                                rows above and below stay in cache            */
-  int32_t run_nodes;        /* consecutive nodes of a row per run             */
+  int32_t run_nodes;        /* consecutive nodes of a row per run (default 16,
+                               64 on the row-window walk)                     */
   int32_t nt_stores;        /* 1: non-temporal output stores, 2: plain (the
                                default)                                      */
+  int32_t row_window;       /* 1-ring operators on columns of more than 32
+                               levels: 1 walk rows reusing the previous
+                               node's column loads (the default), 2 gather
+                               every slot per node                            */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;

@@ -71,7 +71,7 @@ struct atlas_mesh_s {
   size_t scratch_bytes = 0;
   Shape shape[OP_COUNT][3];
   std::mutex order_mu;
-  std::map<std::pair<int, int>, const int32_t*> orders;   // (band rows, run) -> device node order
+  std::map<std::pair<int, int>, NodeOrder> orders;   // (band rows, run) -> device node order
 
   ~atlas_mesh_s() {
     if (device >= 0) {
@@ -98,16 +98,20 @@ struct atlas_mesh_s {
   const DevTables& tables(int dtype) const { return dtype == ATLAS_F64 ? tab64 : tab32; }
 
   // Device node order for a launch shape, built and uploaded on first use.
-  const int32_t* order(const Shape& sh) {
+  NodeOrder order(const Shape& sh) {
     const std::pair<int, int> key(band_rows_of(sh), run_nodes_of(sh));
     std::lock_guard<std::mutex> lk(order_mu);
     auto it = orders.find(key);
     if (it != orders.end()) return it->second;
-    std::vector<int32_t> ord;
+    std::vector<int32_t> ord, runs;
     build_band_order(host, key.first, key.second, ord);
-    const int32_t* d = upload(ord);
-    orders[key] = d;
-    return d;
+    build_band_runs(host, key.first, key.second, runs);
+    NodeOrder no;
+    no.order = upload(ord);
+    no.runs = upload(runs);
+    no.nruns = (int64_t)runs.size() / 2;
+    orders[key] = no;
+    return no;
   }
 };
 
@@ -181,6 +185,7 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->band_rows = s.band_rows;
   t->run_nodes = s.run_nodes;
   t->nt_stores = s.nt_stores;
+  t->row_window = s.row_window;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -211,6 +216,9 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.run_nodes = t->run_nodes;
   if (t->nt_stores < 0 || t->nt_stores > 2) return fail(ATLAS_EINVAL, "nt_stores must be 0, 1 or 2");
   s.nt_stores = t->nt_stores;
+  if (t->row_window < 0 || t->row_window > 2) return fail(ATLAS_EINVAL, "row_window must be 0, 1 or 2");
+  s.row_window = t->row_window;
+
   return ATLAS_OK;
 }
 
@@ -231,8 +239,10 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   if (overlaps(in, nin, out, nout)) return fail(ATLAS_EINVAL, "output overlaps input");
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
-  const Shape& sh = shape_override ? *shape_override : mesh->shape[op][dtype];
-  const int32_t* order = nullptr;
+  Shape sh = shape_override ? *shape_override : mesh->shape[op][dtype];
+  // the row-window walk works best on long runs
+  if (sh.run_nodes == 0 && uses_window(op, nlev, sh)) sh.run_nodes = kDefaultWindowRunNodes;
+  NodeOrder order;
   try {
     order = mesh->order(sh);
   } catch (const std::bad_alloc&) {
@@ -494,13 +504,20 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
     }
     return ATLAS_OK;
   };
-  // stage 1: column mapping (lanes per node, slices per iteration)
+  // stage 1: column mapping (row-window walk, or lanes per node) and slices per iteration
   {
+    for (int u = 1; u <= 3; ++u) {
+      if (!uses_window(o, nlev, Shape())) break;
+      Shape s;
+      s.slices_per_iter = u;
+      if ((rc = time_shape(s))) goto done;
+    }
     const int ps[] = {16, 32, 64};
     for (int p : ps) {
       if (nlev <= 32 && p != 16) continue;   // short columns always use nlev lanes
       for (int u = 1; u <= 3; ++u) {
         Shape s;
+        s.row_window = 2;
         s.lanes_per_node = nlev <= 32 ? 0 : p;
         s.slices_per_iter = u;
         if ((rc = time_shape(s))) goto done;
@@ -551,7 +568,7 @@ done:
 
 struct atlas_batch_s {
   atlas_mesh_t mesh = nullptr;
-  const int32_t* order = nullptr;   // owned by the mesh
+  NodeOrder order;                  // owned by the mesh
   int dtype = 0;
   uint32_t mask = 0;
   Shape shape;
@@ -603,11 +620,11 @@ int plan_upload(atlas_batch_s* b) {
       host[t].in = b->descs[t].in[o];
       host[t].out = b->descs[t].out[o];
       host[t].nlev = L;
-      host[t].lanes = lanes_per_node(L, b->shape);
-      host[t].unroll = slices_per_iter(L, b->shape);
-      host[t].reserved = 0;
+      host[t].window = uses_window(o, L, b->shape) ? 1 : 0;
+      host[t].lanes = host[t].window ? 64 : lanes_per_node(L, b->shape);
+      host[t].unroll = host[t].window ? window_slices(L, b->shape) : slices_per_iter(L, b->shape);
       host[t].tile_begin = tile;
-      tile += tiles_for(V, L, b->shape);
+      tile += tiles_for(o, b->order, V, L, b->shape);
     }
     b->total[o] = tile;
     void* p = nullptr;

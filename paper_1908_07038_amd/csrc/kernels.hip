@@ -31,6 +31,8 @@
 // contiguous part of the order (whole bands) in its own L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.hpp"
 
 namespace atlasnabla {
@@ -99,8 +101,27 @@ __device__ __forceinline__ void st2(bf16_t* p, float x, float y) {
   st_raw<NT>(reinterpret_cast<uint32_t*>(p), f32_to_bf16(x) | (f32_to_bf16(y) << 16));
 }
 
+// Read-only table data read through the constant address space: with a
+// wave-uniform address the compiler fetches it with scalar loads into scalar
+// registers.  Valid because no kernel writes the tables.
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+__device__ __forceinline__ int32_t ld_uniform(const int32_t* p) { return ld_const(p); }
+__device__ __forceinline__ float2 ld_uniform(const float2* p) {
+  const float* q = reinterpret_cast<const float*>(p);
+  return make_float2(ld_const(q), ld_const(q + 1));
+}
+__device__ __forceinline__ double2 ld_uniform(const double2* p) {
+  const double* q = reinterpret_cast<const double*>(p);
+  return make_double2(ld_const(q), ld_const(q + 1));
+}
+
 struct Args {
   const int32_t* order; // [V] node processing order (a permutation)
+  const int32_t* runs;  // [nruns][2] (first node, count): the same order as row runs
+  int64_t nruns;
   const int32_t* nbr;   // [V][8] neighbour table or [V][24] two-ring table
   const void* coef;     // coefficient pairs or two-ring weights (same row layout)
   const void* in;
@@ -108,7 +129,7 @@ struct Args {
   int64_t V;
   int32_t L;            // levels
   int32_t P;            // lanes per node (64 / P nodes per wave)
-  int32_t npw;          // node groups per wave per workgroup
+  int32_t npw;          // node groups (or runs) per wave per workgroup
   int32_t nt;           // non-temporal output stores
 };
 
@@ -277,9 +298,237 @@ __device__ __forceinline__ void run_group(const Args& a, int64_t gbase, int lane
     if (__all(cnt <= 18)) run_lap<S, 18, U>(a, nd, ok, t);
     else run_lap<S, kLapStride - 1, 1>(a, nd, ok, t);
   } else {
-    const int deg = a.nbr[nd * 8 + 7];
+    const int deg = a.nbr[nd * 8 + 7] & 0xff;
     if (__all(deg == 6)) run_1ring<S, OP, 6, U>(a, nd, ok, t);
     else run_1ring<S, OP, 7, 1>(a, nd, ok, t);
+  }
+}
+
+// ---- row-window walk (1-ring operators, columns of more than 32 levels) ----
+//
+// A wave walks a run of consecutive nodes of one latitude row, 64 lanes =
+// 64 levels, U slices of the column at once.  For a window-eligible node the
+// slots in neighbour order are [row above (cu), left, right, row below (cl)],
+// the previous node's self and right neighbour are this node's left and self,
+// and the previous node's last neighbour above (below) is this node's first
+// one above (below).  So a node needs only 1 + (cu - 1) + (cl - 1) new column
+// loads (3 for the usual cu = cl = 2) instead of deg + 1.  Other nodes (run
+// starts, polar rows, neighbours wrapping past the zero meridian) load every
+// slot.  Either way the values are combined in slot order with the same fused
+// multiply-adds as the per-lane path, so all paths give identical bits.
+
+template <class S, int OP>
+struct WinT {
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  static constexpr bool kVecIn = (OP == OP_DIV || OP == OP_GRADT);
+  using X = typename std::conditional<kVecIn, C2, C>::type;
+  static __device__ __forceinline__ X ld(const S* __restrict__ in, uint32_t idx) {
+    if constexpr (kVecIn) return ld2(in + 2 * (size_t)idx);
+    else return ld1(in + (size_t)idx);
+  }
+};
+
+// Combine deg slot values (slot order) with the node's coefficients and store.
+template <class S, int OP, int DEG>
+__device__ __forceinline__ void win_emit(S* __restrict__ out, uint32_t o, bool st, int nt,
+                                         const typename WinT<S, OP>::X x0, const typename WinT<S, OP>::X* v,
+                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
+  using C = typename Traits<S>::C;
+  if constexpr (OP == OP_GRAD || OP == OP_DIVT) {
+    C ax, ay;
+    if constexpr (OP == OP_GRAD) {
+      ax = 0;
+      ay = 0;
+#pragma unroll
+      for (int s = 0; s < DEG; ++s) {
+        const C d = v[s] - x0;
+        ax = fma(cf[s].x, d, ax);
+        ay = fma(cf[s].y, d, ay);
+      }
+    } else {
+      ax = dg.x * x0;
+      ay = dg.y * x0;
+#pragma unroll
+      for (int s = 0; s < DEG; ++s) {
+        ax = fma(cf[s].x, v[s], ax);
+        ay = fma(cf[s].y, v[s], ay);
+      }
+    }
+    if (st) {
+      if (nt) st2<true>(out + 2 * (size_t)o, ax, ay);
+      else st2<false>(out + 2 * (size_t)o, ax, ay);
+    }
+  } else {
+    C acc = dg.x * x0.x;
+    acc = fma(dg.y, x0.y, acc);
+#pragma unroll
+    for (int s = 0; s < DEG; ++s) {
+      acc = fma(cf[s].x, v[s].x, acc);
+      acc = fma(cf[s].y, v[s].y, acc);
+    }
+    if (st) {
+      if (nt) st1<true>(out + (size_t)o, acc);
+      else st1<false>(out + (size_t)o, acc);
+    }
+  }
+}
+
+// Run-time choice among register values, written as element-wise selects so
+// that no private array is indexed at run time.
+__device__ __forceinline__ float pick3(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
+__device__ __forceinline__ double pick3(int k, double a, double b, double c) { return k == 0 ? a : (k == 1 ? b : c); }
+__device__ __forceinline__ float2 pick3(int k, float2 a, float2 b, float2 c) {
+  return make_float2(pick3(k, a.x, b.x, c.x), pick3(k, a.y, b.y, c.y));
+}
+__device__ __forceinline__ double2 pick3(int k, double2 a, double2 b, double2 c) {
+  return make_double2(pick3(k, a.x, b.x, c.x), pick3(k, a.y, b.y, c.y));
+}
+template <class T>
+__device__ __forceinline__ T pick4(int k, T a, T b, T c, T d) { return k == 3 ? d : pick3(k, a, b, c); }
+
+template <class S, int OP, int U>
+struct WinState {
+  typename WinT<S, OP>::X self[U], right[U], up[U], lo[U];
+};
+
+// Full step: every slot loaded (slot order), one slice at a time.
+template <class S, int OP, int U>
+__device__ __forceinline__ void win_full(const Args& a, int32_t i, const int32_t* nbp, int deg, int cu, bool eligible,
+                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
+                                         const uint32_t* kc, const bool* st, WinState<S, OP, U>& w) {
+  using X = typename WinT<S, OP>::X;
+  const S* __restrict__ in = static_cast<const S*>(a.in);
+  const uint32_t L = (uint32_t)a.L;
+  uint32_t off[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) off[s] = (uint32_t)ld_uniform(nbp + s) * L;   // padded with the node itself
+  const uint32_t self = (uint32_t)i * L;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    X v[7];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) v[s] = WinT<S, OP>::ld(in, off[s] + kc[u]);
+    const X x0 = WinT<S, OP>::ld(in, self + kc[u]);
+    S* out = static_cast<S*>(a.out);
+    switch (deg) {
+      case 6: win_emit<S, OP, 6>(out, self + kc[u], st[u], a.nt, x0, v, cf, dg); break;
+      case 5: win_emit<S, OP, 5>(out, self + kc[u], st[u], a.nt, x0, v, cf, dg); break;
+      case 7: win_emit<S, OP, 7>(out, self + kc[u], st[u], a.nt, x0, v, cf, dg); break;
+      case 4: win_emit<S, OP, 4>(out, self + kc[u], st[u], a.nt, x0, v, cf, dg); break;
+      default: win_emit<S, OP, 3>(out, self + kc[u], st[u], a.nt, x0, v, cf, dg); break;
+    }
+    if (eligible) {
+      // eligible nodes have cu in 1..3 and deg = cu + cl + 2 with cl in 1..3
+      w.self[u] = x0;
+      w.right[u] = pick3(cu - 1, v[2], v[3], v[4]);
+      w.up[u] = pick3(cu - 1, v[0], v[1], v[2]);
+      w.lo[u] = pick4(deg - 4, v[3], v[4], v[5], v[6]);
+    }
+  }
+}
+
+// Window step of a window-eligible node with CU neighbours above and CL
+// below: loads only the columns that are new to the window (the right
+// neighbour, above 2..CU, below 2..CL) and slides the window by one node.
+template <class S, int OP, int U, int CU, int CL>
+__device__ __forceinline__ void win_step(const Args& a, int32_t i, const int32_t* nbp,
+                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
+                                         const uint32_t* kc, const bool* st, WinState<S, OP, U>& w) {
+  using X = typename WinT<S, OP>::X;
+  constexpr int DEG = CU + CL + 2;
+  const S* __restrict__ in = static_cast<const S*>(a.in);
+  const uint32_t L = (uint32_t)a.L;
+  uint32_t offu[CU > 1 ? CU - 1 : 1], offl[CL > 1 ? CL - 1 : 1];
+#pragma unroll
+  for (int t = 1; t < CU; ++t) offu[t - 1] = (uint32_t)ld_uniform(nbp + t) * L;
+#pragma unroll
+  for (int t = 1; t < CL; ++t) offl[t - 1] = (uint32_t)ld_uniform(nbp + CU + 2 + t) * L;
+  const uint32_t offr = (uint32_t)(i + 1) * L;
+  X nu[U][CU > 1 ? CU - 1 : 1], nl[U][CL > 1 ? CL - 1 : 1], nr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    nr[u] = WinT<S, OP>::ld(in, offr + kc[u]);
+#pragma unroll
+    for (int t = 0; t < CU - 1; ++t) nu[u][t] = WinT<S, OP>::ld(in, offu[t] + kc[u]);
+#pragma unroll
+    for (int t = 0; t < CL - 1; ++t) nl[u][t] = WinT<S, OP>::ld(in, offl[t] + kc[u]);
+  }
+  const uint32_t self = (uint32_t)i * L;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    X v[DEG];
+    v[0] = w.up[u];
+#pragma unroll
+    for (int t = 1; t < CU; ++t) v[t] = nu[u][t - 1];
+    v[CU] = w.self[u];           // left neighbour = previous node
+    v[CU + 1] = nr[u];           // right neighbour
+    v[CU + 2] = w.lo[u];
+#pragma unroll
+    for (int t = 1; t < CL; ++t) v[CU + 2 + t] = nl[u][t - 1];
+    const X x0 = w.right[u];     // this node = previous right neighbour
+    win_emit<S, OP, DEG>(static_cast<S*>(a.out), self + kc[u], st[u], a.nt, x0, v, cf, dg);
+    w.self[u] = x0;
+    w.right[u] = nr[u];
+    w.up[u] = v[CU - 1];
+    w.lo[u] = v[DEG - 1];
+  }
+}
+
+// One wave walks one run of consecutive nodes of a row, U level slices of 64
+// at a time; the first node of a run, and any node outside the window pattern,
+// takes a full step that reloads every slot.
+template <class S, int OP, int U>
+__device__ __forceinline__ void win_run(const Args& a, int32_t i0, int cnt, int lane) {
+  using C2 = typename Traits<S>::C2;
+  const uint32_t L = (uint32_t)a.L;
+  for (uint32_t k0 = 0; k0 < L; k0 += 64u * U) {
+    uint32_t kc[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t k = k0 + 64u * u + (uint32_t)lane;
+      st[u] = k < L;
+      kc[u] = k < L ? k : L - 1;
+    }
+    WinState<S, OP, U> w;
+    bool have = false;
+    for (int n = 0; n < cnt; ++n) {
+      const int32_t i = i0 + n;
+      const int32_t* nbp = a.nbr + (int64_t)i * 8;
+      const int meta = ld_uniform(nbp + 7);
+      const int deg = meta & 0xff;
+      const int cu = (meta >> 8) & 0xff;
+      const bool eligible = (meta >> 16) & 1;
+      const C2* cfp = static_cast<const C2*>(a.coef) + (int64_t)i * 8;
+      C2 cf[7];
+#pragma unroll
+      for (int s = 0; s < 7; ++s) cf[s] = ld_uniform(cfp + s);
+      const C2 dg = ld_uniform(cfp + 7);
+      const int cl = deg - cu - 2;
+      if (have && eligible && cu == 2 && cl == 2) win_step<S, OP, U, 2, 2>(a, i, nbp, cf, dg, kc, st, w);
+      else if (have && eligible && cu == 1 && cl == 3) win_step<S, OP, U, 1, 3>(a, i, nbp, cf, dg, kc, st, w);
+      else if (have && eligible && cu == 3 && cl == 1) win_step<S, OP, U, 3, 1>(a, i, nbp, cf, dg, kc, st, w);
+      else if (have && eligible && cu == 1 && cl == 2) win_step<S, OP, U, 1, 2>(a, i, nbp, cf, dg, kc, st, w);
+      else if (have && eligible && cu == 2 && cl == 1) win_step<S, OP, U, 2, 1>(a, i, nbp, cf, dg, kc, st, w);
+      else win_full<S, OP, U>(a, i, nbp, deg, cu, eligible, cf, dg, kc, st, w);
+      have = eligible;
+    }
+  }
+}
+
+// Work of logical block `lb` on the run list: waves_per_block * npw runs.
+template <class S, int OP, int U>
+__device__ __forceinline__ void process_runs(const Args& a, int64_t lb) {
+  const int wpb = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (int r = 0; r < a.npw; ++r) {
+    const int64_t run = (lb * a.npw + r) * wpb + wave;
+    if (run >= a.nruns) break;
+    const int32_t i0 = ld_uniform(a.runs + 2 * run);
+    const int32_t cnt = ld_uniform(a.runs + 2 * run + 1);
+    win_run<S, OP, U>(a, i0, cnt, lane);
   }
 }
 
@@ -310,6 +559,13 @@ __global__ __launch_bounds__(256) void k_op(Args a, int64_t nblocks, int remap) 
   process_block<S, OP, U>(a, lb);
 }
 
+template <class S, int OP, int U>
+__global__ __launch_bounds__(256) void k_win(Args a, int64_t nblocks, int remap) {
+  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
+  if (lb >= nblocks) return;
+  process_runs<S, OP, U>(a, lb);
+}
+
 // Persistent batched form: the global tile index space is the concatenation
 // of each tracer's blocks; every workgroup walks a contiguous range of it.
 template <class S, int OP>
@@ -330,6 +586,16 @@ __global__ __launch_bounds__(256) void k_batched(Args base, const BatchItem* __r
     a.L = items[item].nlev;
     a.P = items[item].lanes;
     const int64_t lb2 = tile - items[item].tile_begin;
+    if constexpr (OP != OP_LAP) {
+      if (items[item].window) {
+        switch (items[item].unroll) {
+          case 1: process_runs<S, OP, 1>(a, lb2); break;
+          case 2: process_runs<S, OP, 2>(a, lb2); break;
+          default: process_runs<S, OP, 3>(a, lb2); break;
+        }
+        continue;
+      }
+    }
     switch (items[item].unroll) {
       case 1: process_block<S, OP, 1>(a, lb2); break;
       case 2: process_block<S, OP, 2>(a, lb2); break;
@@ -432,10 +698,12 @@ __global__ __launch_bounds__(256) void k_cons_final(const double* __restrict__ p
 
 // ---- dispatch ---------------------------------------------------------------
 
-Args make_args(int op, const DevTables& t, const int32_t* order, int64_t V, int nlev, const void* in, void* out,
+Args make_args(int op, const DevTables& t, const NodeOrder& ord, int64_t V, int nlev, const void* in, void* out,
                const Shape& sh) {
   Args a;
-  a.order = order;
+  a.order = ord.order;
+  a.runs = ord.runs;
+  a.nruns = ord.nruns;
   if (op == OP_LAP) {
     a.nbr = t.lap_nbr;
     a.coef = t.lap_w;
@@ -454,6 +722,16 @@ Args make_args(int op, const DevTables& t, const int32_t* order, int64_t V, int 
 }
 
 template <class S, int OP>
+hipError_t launch_win(const Args& a, int U, dim3 g, dim3 b, int64_t nblocks, int remap, hipStream_t st) {
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_win<S, OP, 1>), g, b, 0, st, a, nblocks, remap); break;
+    case 2: hipLaunchKernelGGL((k_win<S, OP, 2>), g, b, 0, st, a, nblocks, remap); break;
+    default: hipLaunchKernelGGL((k_win<S, OP, 3>), g, b, 0, st, a, nblocks, remap); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S, int OP>
 hipError_t launch_u(const Args& a, int U, dim3 g, dim3 b, int64_t nblocks, int remap, hipStream_t st) {
   switch (U) {
     case 1: hipLaunchKernelGGL((k_op<S, OP, 1>), g, b, 0, st, a, nblocks, remap); break;
@@ -464,9 +742,19 @@ hipError_t launch_u(const Args& a, int U, dim3 g, dim3 b, int64_t nblocks, int r
 }
 
 template <class S>
-hipError_t launch_op_t(int op, const Args& a, int U, int64_t nblocks, const Shape& sh, hipStream_t st) {
+hipError_t launch_op_t(int op, const Args& a, int U, int64_t nblocks, bool window, const Shape& sh,
+                       hipStream_t st) {
   const int64_t grid = sh.xcd_remap ? (nblocks + 7) / 8 * 8 : nblocks;
   const dim3 g((unsigned)grid), b((unsigned)(64 * sh.waves_per_block));
+  if (window) {
+    switch (op) {
+      case OP_GRAD: return launch_win<S, OP_GRAD>(a, U, g, b, nblocks, sh.xcd_remap, st);
+      case OP_DIV: return launch_win<S, OP_DIV>(a, U, g, b, nblocks, sh.xcd_remap, st);
+      case OP_GRADT: return launch_win<S, OP_GRADT>(a, U, g, b, nblocks, sh.xcd_remap, st);
+      case OP_DIVT: return launch_win<S, OP_DIVT>(a, U, g, b, nblocks, sh.xcd_remap, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (op) {
     case OP_GRAD: return launch_u<S, OP_GRAD>(a, U, g, b, nblocks, sh.xcd_remap, st);
     case OP_DIV: return launch_u<S, OP_DIV>(a, U, g, b, nblocks, sh.xcd_remap, st);
@@ -497,6 +785,10 @@ hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int n
 
 }  // namespace
 
+bool uses_window(int op, int nlev, const Shape& sh) {
+  return op != OP_LAP && nlev > 32 && sh.row_window != 2;
+}
+
 int lanes_per_node(int nlev, const Shape& sh) {
   if (nlev <= 32) return nlev;
   if (sh.lanes_per_node > 0) return sh.lanes_per_node;
@@ -522,24 +814,36 @@ int slices_per_iter(int nlev, const Shape& sh) {
   return U < nsl ? U : nsl;
 }
 
-int64_t blocks_for(int64_t V, int nlev, const Shape& sh) {
+int64_t blocks_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& sh) {
+  if (uses_window(op, nlev, sh)) {
+    const int64_t per_block = (int64_t)sh.waves_per_block * sh.nodes_per_wave;
+    return (ord.nruns + per_block - 1) / per_block;
+  }
   const int G = 64 / lanes_per_node(nlev, sh);
   const int64_t per_block = (int64_t)sh.waves_per_block * sh.nodes_per_wave * G;
   return (V + per_block - 1) / per_block;
 }
 
-hipError_t launch_op(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V, int nlev,
+hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V, int nlev,
                      const void* in, void* out, const Shape& shape, hipStream_t stream) {
   if (op == OP_LAP && t.lap_stride != kLapStride) return hipErrorInvalidValue;
-  const Args a = make_args(op, t, order, V, nlev, in, out, shape);
-  const int U = slices_per_iter(nlev, shape);
-  const int64_t nblocks = blocks_for(V, nlev, shape);
+  const Args a = make_args(op, t, ord, V, nlev, in, out, shape);
+  const bool window = uses_window(op, nlev, shape);
+  const int U = window ? window_slices(nlev, shape) : slices_per_iter(nlev, shape);
+  const int64_t nblocks = blocks_for(op, ord, V, nlev, shape);
   switch (dtype) {
-    case DT_F64: return launch_op_t<double>(op, a, U, nblocks, shape, stream);
-    case DT_F32: return launch_op_t<float>(op, a, U, nblocks, shape, stream);
-    case DT_BF16: return launch_op_t<bf16_t>(op, a, U, nblocks, shape, stream);
+    case DT_F64: return launch_op_t<double>(op, a, U, nblocks, window, shape, stream);
+    case DT_F32: return launch_op_t<float>(op, a, U, nblocks, window, shape, stream);
+    case DT_BF16: return launch_op_t<bf16_t>(op, a, U, nblocks, window, shape, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+int window_slices(int nlev, const Shape& sh) {
+  const int nsl = (nlev + 63) / 64;
+  int U = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
+  if (U > 3) U = 3;
+  return U < nsl ? U : nsl;
 }
 
 int conservation_parts(int64_t V, int nlev) {
@@ -574,12 +878,14 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
   return hipGetLastError();
 }
 
-int64_t tiles_for(int64_t V, int nlev, const Shape& shape) { return blocks_for(V, nlev, shape); }
+int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape) {
+  return blocks_for(op, ord, V, nlev, shape);
+}
 
-hipError_t launch_batched(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V,
+hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V,
                           const BatchItem* items, int nitems, int64_t total_tiles, const Shape& shape, int num_cus,
                           hipStream_t stream) {
-  Args a = make_args(op, t, order, V, 1, nullptr, nullptr, shape);
+  Args a = make_args(op, t, ord, V, 1, nullptr, nullptr, shape);
   switch (dtype) {
     case DT_F64: return launch_batched_t<double>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
     case DT_F32: return launch_batched_t<float>(op, a, items, nitems, total_tiles, shape, num_cus, stream);

@@ -28,25 +28,40 @@ struct Shape {
   int lanes_per_node = 0;    // 0: chosen from nlev; else 16, 32 or 64 (nlev > 32)
   int slices_per_iter = 0;   // 0: 3 (capped by the slice count); else 1..3
   int band_rows = 0;         // 0: kDefaultBandRows; rows per band of the node order
-  int run_nodes = 0;         // 0: kDefaultRunNodes; consecutive nodes per run of the order
+  int run_nodes = 0;         // 0: kDefaultRunNodes (kDefaultWindowRunNodes on the row-window walk)
   int nt_stores = 0;         // 0: default (off), 1: non-temporal output stores, 2: off
+  int row_window = 0;        // 0: default (on), 1: on, 2: off -- row-window walk of 1-ring operators
 };
 
 constexpr int kDefaultBandRows = 32;
 constexpr int kDefaultRunNodes = 16;
+constexpr int kDefaultWindowRunNodes = 64;
 inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
 inline int run_nodes_of(const Shape& s) { return s.run_nodes > 0 ? s.run_nodes : kDefaultRunNodes; }
 inline bool nt_of(const Shape& s) { return s.nt_stores == 1; }
 
+// Device node order of a launch shape: the permutation of the nodes and the
+// same order as runs of consecutive nodes (first node, count).
+struct NodeOrder {
+  const int32_t* order = nullptr;
+  const int32_t* runs = nullptr;
+  int64_t nruns = 0;
+};
+
+// Whether an operator walks rows with a register window (1-ring operators
+// on columns of more than 32 levels, unless the shape turns it off).
+bool uses_window(int op, int nlev, const Shape& sh);
 // Lanes per node: nlev for columns of at most 32 levels (64 / nlev nodes per
 // wave), else the width in {64, 32, 16} that wastes the fewest lanes.
 int lanes_per_node(int nlev, const Shape& sh);
-// Level slices per loop iteration of a lane (1..3).
+// Level slices per loop iteration of a lane (1..3), per-lane path.
 int slices_per_iter(int nlev, const Shape& sh);
+// Level slices (of 64) in flight per node step, row-window path (1..3).
+int window_slices(int nlev, const Shape& sh);
 
 // Single-field operator launch; in/out are device pointers of the dtype and
-// `order` the device node order (a permutation of 0..V-1) work follows.
-hipError_t launch_op(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V, int nlev,
+// `ord` the device node order work follows.
+hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V, int nlev,
                      const void* in, void* out, const Shape& shape, hipStream_t stream);
 
 // Conservation sums: partial [nparts][nlev][2] doubles of scratch, then the
@@ -62,12 +77,12 @@ struct BatchItem {
   void* out;
   int32_t nlev;
   int32_t lanes;         // lanes_per_node(nlev)
-  int32_t unroll;        // slices_per_iter(nlev)
-  int32_t reserved;
+  int32_t unroll;        // slices per iteration (window_slices or slices_per_iter)
+  int32_t window;        // uses_window(op, nlev)
   int64_t tile_begin;    // first global tile of this tracer
 };
-int64_t tiles_for(int64_t V, int nlev, const Shape& shape);
-hipError_t launch_batched(int op, int dtype, const DevTables& t, const int32_t* order, int64_t V,
+int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape);
+hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V,
                           const BatchItem* items, int nitems, int64_t total_tiles,
                           const Shape& shape, int num_cus, hipStream_t stream);
 

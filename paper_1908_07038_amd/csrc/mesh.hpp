@@ -50,7 +50,7 @@ struct HostMesh {
 // Per-node operator tables in FP64, later rounded to FP32 for the FP32 and
 // BF16 kernels.  Record layout per node (kEll slots):
 //   nbr8[i][s]   neighbour of slot s (s < deg), i itself for s >= deg,
-//   nbr8[i][7]   deg
+//   nbr8[i][7]   deg | cu << 8 | window-eligible << 16 (see window_meta)
 //   coef[i][s]   (x, y) coefficient pair of slot s, (0, 0) padding,
 //   coef[i][7]   the diagonal pair of the operator.
 struct OpTables {
@@ -83,5 +83,10 @@ void build_op_tables(const HostMesh& m, OpTables& t);
 // in cache (only rows at band edges are fetched twice), while the nodes of a
 // run, whose columns share cache lines, are processed together.
 void build_band_order(const HostMesh& m, int band_rows, int run_nodes, std::vector<int32_t>& order);
+// The same runs as pairs (first node, node count), in the same order.
+void build_band_runs(const HostMesh& m, int band_rows, int run_nodes, std::vector<int32_t>& runs);
+// Row-window metadata of a node (see mesh_build.cpp); packed in the header
+// slot of the neighbour table above the degree: deg | meta << 8.
+int window_meta(const HostMesh& m, int64_t i, int deg);
 
 }  // namespace atlasnabla

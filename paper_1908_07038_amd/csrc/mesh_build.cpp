@@ -391,6 +391,37 @@ void build_host_mesh(int N, double radius, HostMesh& m) {
     }
 }
 
+// Row-window metadata of node i (packed above the degree in the header slot):
+// bits 0..7 the number cu of neighbours in the row above, bit 8 set when the
+// node's slots, in neighbour order, read [row above (cu), left, right, row
+// below] with the row-above and row-below neighbours consecutive in their
+// rows without wrapping past the zero meridian.  Then a walk along the row
+// can reuse the previous node's values: its self and right neighbour become
+// this node's left and self, and the last neighbour above (below) of the
+// previous node is this node's first neighbour above (below).  Polar rows
+// (ladder chords) and nodes whose ranges wrap get 0.
+int window_meta(const HostMesh& m, int64_t i, int deg) {
+  const int k = m.node_row[i];
+  if (k == 0 || k == m.nrows - 1) return 0;
+  const int64_t s0 = m.csr_off[i];
+  const int64_t rk = m.row_off[k], nk = m.row_size[k];
+  const int64_t j = i - rk;
+  if (j == 0 || j == nk - 1) return 0;
+  int cu = 0;
+  while (cu < deg && m.node_row[m.nbr[s0 + cu]] == k - 1) ++cu;
+  const int cl = deg - cu - 2;
+  if (cu < 1 || cl < 1 || cu > 3 || cl > 3) return 0;
+  if (m.nbr[s0 + cu] != i - 1 || m.nbr[s0 + cu + 1] != i + 1) return 0;
+  for (int t = 1; t < cu; ++t)
+    if (m.nbr[s0 + t] != m.nbr[s0 + t - 1] + 1 || m.node_row[m.nbr[s0 + t]] != k - 1) return 0;
+  for (int t = 0; t < cl; ++t) {
+    const int32_t nb = m.nbr[s0 + cu + 2 + t];
+    if (m.node_row[nb] != k + 1) return 0;
+    if (t > 0 && nb != m.nbr[s0 + cu + 2 + t - 1] + 1) return 0;
+  }
+  return cu | (1 << 8);
+}
+
 // Per-slot coefficients (difference / gather form of the edge sums):
 //   a_is = 0.5 sign (east_i . S_e) / V_i     b_is = 0.5 sign (north_i . S_e) / V_i
 //   c_is = 0.5 sign (east_n . S_e) / V_i     d_is = 0.5 sign (north_n . S_e) / V_i
@@ -430,7 +461,7 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
       A += a;
       B += b;
     }
-    t.nbr8[kEll * i + kEll - 1] = deg;
+    t.nbr8[kEll * i + kEll - 1] = deg | (window_meta(m, i, deg) << 8);
     const int64_t dg = 2 * (kEll * i + kEll - 1);
     t.grad[dg] = A; t.grad[dg + 1] = B;
     t.div[dg] = A; t.div[dg + 1] = B;
@@ -466,13 +497,13 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
         if (en.node == node) { en.w += w; return; }
       ring.push_back({node, w});
     };
-    const int deg_i = t.nbr8[kEll * i + kEll - 1];
+    const int deg_i = t.nbr8[kEll * i + kEll - 1] & 0xff;
     for (int s = -1; s < deg_i; ++s) {
       // s = -1: the node itself with the diagonal pair (A_i, B_i)
       const int64_t j = s < 0 ? i : t.nbr8[kEll * i + s];
       const int64_t cs = 2 * (kEll * i + (s < 0 ? kEll - 1 : s));
       const double alpha = t.div[cs], beta = t.div[cs + 1];
-      const int deg_j = t.nbr8[kEll * j + kEll - 1];
+      const int deg_j = t.nbr8[kEll * j + kEll - 1] & 0xff;
       for (int u = 0; u < deg_j; ++u) {
         const int32_t mm = t.nbr8[kEll * j + u];
         const int64_t cu = 2 * (kEll * j + u);
@@ -501,6 +532,27 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
       w[k - fstart[i]] = flat[k].w;
     }
     nb[stride - 1] = cnt[i];
+  }
+}
+
+void build_band_runs(const HostMesh& m, int band_rows, int run_nodes, std::vector<int32_t>& runs_out) {
+  if (band_rows < 1 || run_nodes < 1) throw std::runtime_error("band_rows and run_nodes must be >= 1");
+  struct Run { int32_t j, n, row; };
+  std::vector<Run> runs;
+  runs_out.clear();
+  for (int k0 = 0; k0 < m.nrows; k0 += band_rows) {
+    const int k1 = std::min(m.nrows, k0 + band_rows);
+    runs.clear();
+    for (int k = k0; k < k1; ++k)
+      for (int j = 0; j < m.row_size[k]; j += run_nodes) runs.push_back({j, m.row_size[k], k});
+    std::sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) {
+      const int64_t a = (int64_t)x.j * y.n, b = (int64_t)y.j * x.n;
+      return a != b ? a < b : x.row < y.row;
+    });
+    for (const Run& r : runs) {
+      runs_out.push_back((int32_t)(m.row_off[r.row] + r.j));
+      runs_out.push_back(std::min(r.n, r.j + run_nodes) - r.j);
+    }
   }
 }
 

@@ -204,10 +204,15 @@ def test_argument_errors():
 
 
 SHAPES = [dict(lanes_per_node=p, slices_per_iter=u, waves_per_block=w, nodes_per_wave=n, xcd_remap=x,
-               band_rows=h, run_nodes=r, nt_stores=nt)
-          for (p, u, w, n, x, h, r, nt) in [(16, 1, 1, 1, 2, 1, 1, 1), (16, 3, 4, 2, 1, 0, 0, 2),
-                                            (32, 2, 2, 4, 1, 7, 3, 1), (64, 3, 4, 8, 2, 64, 64, 2),
-                                            (64, 1, 1, 3, 1, 1000, 5, 1), (32, 3, 4, 1, 2, 2, 1000, 2)]]
+               band_rows=h, run_nodes=r, nt_stores=nt, row_window=rw)
+          for (p, u, w, n, x, h, r, nt, rw, nw) in [
+              (16, 1, 1, 1, 2, 1, 1, 1, 2, 0), (16, 3, 4, 2, 1, 0, 0, 2, 2, 0),
+              (32, 2, 2, 4, 1, 7, 3, 1, 2, 0), (64, 3, 4, 8, 2, 64, 64, 2, 2, 0),
+              (64, 1, 1, 3, 1, 1000, 5, 1, 2, 0), (32, 3, 4, 1, 2, 2, 1000, 2, 2, 0),
+              (0, 1, 1, 1, 2, 1, 1, 1, 1, 1), (0, 3, 4, 2, 1, 0, 0, 2, 1, 2),
+              (0, 2, 2, 4, 1, 7, 3, 1, 1, 1), (0, 3, 4, 8, 2, 64, 64, 2, 0, 2),
+              (0, 1, 1, 3, 1, 1000, 5, 1, 1, 2), (0, 2, 4, 1, 2, 2, 1000, 2, 1, 1),
+              (0, 3, 2, 3, 1, 5, 7, 2, 1, 2), (0, 1, 4, 1, 1, 3, 2, 2, 0, 1)]]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
