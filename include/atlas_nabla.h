@@ -220,6 +220,10 @@ typedef struct {
                                levels: 1 walk rows reusing the previous
                                node's column loads (the default), 2 gather
                                every slot per node                            */
+  int32_t lds_tiles;        /* FP32/FP64 columns of more than 32 levels:
+                               1 stage each tile of nodes and the columns its
+                               stencils read in LDS, 0/2 off (the default)    */
+  int32_t tile_kb;          /* LDS budget of one tile in KiB, 8..64 (0: 48)  */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;

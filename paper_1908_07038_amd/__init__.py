@@ -44,7 +44,8 @@ class TuneShape(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("lanes_per_node", ctypes.c_int32), ("slices_per_iter", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32), ("run_nodes", ctypes.c_int32),
-                ("nt_stores", ctypes.c_int32), ("row_window", ctypes.c_int32)]
+                ("nt_stores", ctypes.c_int32), ("row_window", ctypes.c_int32),
+                ("lds_tiles", ctypes.c_int32), ("tile_kb", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -72,6 +72,8 @@ struct atlas_mesh_s {
   Shape shape[OP_COUNT][3];
   std::mutex order_mu;
   std::map<std::pair<int, int>, NodeOrder> orders;   // (band rows, run) -> device node order
+  OpTables host_nbr;                                   // neighbour tables only (tile building)
+  std::map<std::vector<int64_t>, DevTiles> tilings;   // tiling key -> device tiles
 
   ~atlas_mesh_s() {
     if (device >= 0) {
@@ -113,6 +115,31 @@ struct atlas_mesh_s {
     orders[key] = no;
     return no;
   }
+
+  // Device tiles of an LDS-tiled launch, built and uploaded on first use.
+  DevTiles tiles(const TileGeom& g, const Shape& sh) {
+    const std::vector<int64_t> key = {g.ring, band_rows_of(sh), run_nodes_of(sh), g.col_bytes, g.row_bytes, g.budget};
+    std::lock_guard<std::mutex> lk(order_mu);
+    auto it = tilings.find(key);
+    if (it != tilings.end()) return it->second;
+    HaloTiles ht;
+    build_halo_tiles(host, host_nbr, g.ring, band_rows_of(sh), run_nodes_of(sh), g.col_bytes, g.row_bytes,
+                     g.budget, ht);
+    DevTiles dt;
+    dt.info = upload(ht.info);
+    dt.segs = upload(ht.segs);
+    dt.runs = upload(ht.runs);
+    dt.loc = upload(ht.loc);
+    dt.ntiles = ht.ntiles;
+    dt.col_bytes = g.col_bytes;
+    dt.row_bytes = g.row_bytes;
+    int64_t lds = 0;
+    for (int64_t t = 0; t < ht.ntiles; ++t)
+      lds = std::max(lds, ht.info[4 * t + 2] * g.col_bytes + ht.info[4 * t + 3] * g.row_bytes);
+    dt.lds_bytes = (uint32_t)lds;
+    tilings[key] = dt;
+    return dt;
+  }
 };
 
 namespace {
@@ -139,6 +166,9 @@ void upload_tables(atlas_mesh_s& m) {
   m.tab64.lap_w = m.upload(t.lap_w);
   m.tab32.lap_w = m.upload(to_f32(t.lap_w));
   m.vol = m.upload(m.host.vol);
+  m.host_nbr.nbr8 = std::move(t.nbr8);
+  m.host_nbr.lap_nbr = std::move(t.lap_nbr);
+  m.host_nbr.lap_stride = t.lap_stride;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -186,6 +216,8 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->run_nodes = s.run_nodes;
   t->nt_stores = s.nt_stores;
   t->row_window = s.row_window;
+  t->lds_tiles = s.lds_tiles;
+  t->tile_kb = s.tile_kb;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -218,6 +250,10 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.nt_stores = t->nt_stores;
   if (t->row_window < 0 || t->row_window > 2) return fail(ATLAS_EINVAL, "row_window must be 0, 1 or 2");
   s.row_window = t->row_window;
+  if (t->lds_tiles < 0 || t->lds_tiles > 2) return fail(ATLAS_EINVAL, "lds_tiles must be 0, 1 or 2");
+  s.lds_tiles = t->lds_tiles;
+  if (t->tile_kb != 0 && (t->tile_kb < 8 || t->tile_kb > 64)) return fail(ATLAS_EINVAL, "tile_kb must be 0 or 8..64");
+  s.tile_kb = t->tile_kb;
 
   return ATLAS_OK;
 }
@@ -240,6 +276,23 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
   Shape sh = shape_override ? *shape_override : mesh->shape[op][dtype];
+  const TileGeom tg = uses_tiles(op, dtype, nlev, sh) ? tile_geom(op, dtype, nlev, sh) : TileGeom();
+  if (tg.KL > 0) {   // tiles asked for and a tile geometry fits the budget
+    DevTiles dt;
+    try {
+      // tilings depend on the byte sizes only; the level chunk is the call's
+      dt = mesh->tiles(tg, sh);
+      dt.KL = tg.KL;
+      dt.nchunks = tg.nchunks;
+    } catch (const std::bad_alloc&) {
+      return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
+    } catch (const std::exception& ex) {
+      return fail(ATLAS_EHIP, ex.what());
+    }
+    hipError_t e = launch_tiles(op, dtype, mesh->tables(dtype), dt, nlev, in, out, sh, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, kOpName[op]);
+    return ATLAS_OK;
+  }
   // the row-window walk works best on long runs
   if (sh.run_nodes == 0 && uses_window(op, nlev, sh)) sh.run_nodes = kDefaultWindowRunNodes;
   NodeOrder order;

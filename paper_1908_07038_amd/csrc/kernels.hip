@@ -604,6 +604,240 @@ __global__ __launch_bounds__(256) void k_batched(Args base, const BatchItem* __r
   }
 }
 
+// ---- LDS tiles -------------------------------------------------------------------
+//
+// A workgroup takes one tile: a set of nodes (runs of consecutive nodes from
+// the band order) and the sorted set of every column their stencils read,
+// stored as segments of consecutive nodes.  Columns of consecutive nodes are
+// contiguous in memory, so each segment is one contiguous block, which the
+// waves copy with direct global->LDS loads (64 dwords per instruction, no
+// registers involved) together with the tile's table rows (LDS positions and
+// coefficients); one wait and one barrier end the copy.  Each wave then takes
+// nodes of the tile in turn, 64 lanes = 64 levels, and reads its stencil and
+// tables from LDS; only the output goes back to memory.  No global load sits
+// on a node's critical path, every wave keeps many independent loads in
+// flight during the copy, and the workgroups sharing a CU overlap each
+// other's copy and compute phases.  Tiles follow the band order, so the halo
+// columns a tile shares with the tiles next to it are L2 hits.
+
+struct TileArgs {
+  const int32_t* info;   // [ntiles + 1][4]: first segment, first run, columns, nodes
+  const int32_t* segs;   // [nseg][2]: first node, count
+  const int32_t* runs;   // [nrun][2]: first node, count
+  const uint16_t* loc;   // [V][stride] LDS positions; last entry: own position | count << 11
+  const void* coef;      // [V][stride] coefficient pairs (ring 1) or weights (ring 2)
+  const void* in;
+  void* out;
+  int64_t ntiles;
+  int32_t L;             // levels
+  int32_t KL;            // levels per chunk (L: whole columns)
+  int32_t nchunks;
+  int32_t nt;
+};
+
+constexpr int kLocCountShift = 11;
+
+typedef __attribute__((address_space(3))) void* lds_vptr;
+
+// Direct loads of nbytes (a multiple of 4) from global src to LDS byte offset
+// dst.  Instruction q of the copy (64 dwords, lane l moves dword 64 q + l)
+// goes to wave (ctr + q) mod W, ctr counting the instructions of the earlier
+// copies of the workgroup, so that small copies spread over the waves.
+__device__ __forceinline__ void dma_copy(const char* src, char* lds, uint32_t dst, uint32_t nbytes, int wave, int W,
+                                         int lane, uint32_t& ctr) {
+  const uint32_t ndw = nbytes >> 2;
+  const uint32_t ninst = (ndw + 63) >> 6;
+  for (uint32_t q = (uint32_t)((wave - (int)(ctr % (uint32_t)W) + W) % W); q < ninst; q += (uint32_t)W) {
+    const uint32_t d = q * 64 + (uint32_t)lane;
+    if (d < ndw) __builtin_amdgcn_global_load_lds(src + 4 * (size_t)d, (lds_vptr)(lds + dst + 256 * q), 4, 0, 0);
+  }
+  ctr += ninst;
+}
+
+template <class T>
+__device__ __forceinline__ T lds_ld(const char* lds, uint32_t off) {
+  return *reinterpret_cast<const T*>(lds + off);
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// LDS positions of a node's entries (wave-uniform): pos[s] for the stencil
+// slots, own position and entry count from the last record entry.
+template <int NREC>
+__device__ __forceinline__ void tile_positions(const char* lds, uint32_t off, uint32_t* pos, uint32_t& self,
+                                               int& cnt) {
+  uint32_t w[NREC / 2];
+#pragma unroll
+  for (int q = 0; q < NREC / 8; ++q) {
+    const uint4 r = lds_ld<uint4>(lds, off + 16 * q);
+    w[4 * q] = uni(r.x);
+    w[4 * q + 1] = uni(r.y);
+    w[4 * q + 2] = uni(r.z);
+    w[4 * q + 3] = uni(r.w);
+  }
+#pragma unroll
+  for (int s = 0; s < NREC - 1; ++s) pos[s] = (s & 1) ? (w[s >> 1] >> 16) : (w[s >> 1] & 0xffffu);
+  const uint32_t last = w[NREC / 2 - 1] >> 16;
+  self = last & ((1u << kLocCountShift) - 1);
+  cnt = (int)(last >> kLocCountShift);
+}
+
+// One node of a 1-ring operator: DEG slots, U slices of 64 levels per step.
+template <class S, int OP, int U, int DEG>
+__device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, uint32_t data_off, uint32_t colB,
+                                           const uint32_t* pos, uint32_t self, const typename Traits<S>::C2* cf,
+                                           typename Traits<S>::C2 dg, uint32_t obase, int klc, int lane) {
+  using X = typename WinT<S, OP>::X;
+  uint32_t so[DEG];
+#pragma unroll
+  for (int s = 0; s < DEG; ++s) so[s] = data_off + pos[s] * colB;
+  const uint32_t xo = data_off + self * colB;
+  S* __restrict__ out = static_cast<S*>(a.out);
+  for (int kb = 0; kb < klc; kb += 64 * U) {
+    X v[U][DEG], x0[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kb + 64 * u + lane;
+      st[u] = k < klc;
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(X);
+#pragma unroll
+      for (int s = 0; s < DEG; ++s) v[u][s] = lds_ld<X>(lds, so[s] + kk);
+      x0[u] = lds_ld<X>(lds, xo + kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      win_emit<S, OP, DEG>(out, obase + (uint32_t)(kb + 64 * u + lane), st[u], a.nt, x0[u], v[u], cf, dg);
+  }
+}
+
+// One node of the two-ring Laplacian: NS entries (padded with the node itself
+// and zero weights, which add exact zeros), sum_m W_im (f_m - f_i).
+template <class S, int U, int NS>
+__device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, uint32_t data_off, uint32_t colB,
+                                           const uint32_t* pos, uint32_t self, const typename Traits<S>::C* w,
+                                           uint32_t obase, int klc, int lane) {
+  using C = typename Traits<S>::C;
+  uint32_t so[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) so[s] = data_off + pos[s] * colB;
+  const uint32_t xo = data_off + self * colB;
+  S* __restrict__ out = static_cast<S*>(a.out);
+  for (int kb = 0; kb < klc; kb += 64 * U) {
+    C v[U][NS], x0[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kb + 64 * u + lane;
+      st[u] = k < klc;
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(C);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_ld<C>(lds, so[s] + kk);
+      x0[u] = lds_ld<C>(lds, xo + kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      C acc = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc = fma(w[s], v[u][s] - x0[u], acc);
+      if (st[u]) {
+        const uint32_t o = obase + (uint32_t)(kb + 64 * u + lane);
+        if (a.nt) st1<true>(out + (size_t)o, acc);
+        else st1<false>(out + (size_t)o, acc);
+      }
+    }
+  }
+}
+
+template <class S, int OP, int U>
+__global__ __launch_bounds__(256) void k_tile(TileArgs a, int64_t nblocks, int remap) {
+  extern __shared__ __align__(16) char lds[];
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  constexpr bool kRing2 = OP == OP_LAP;
+  constexpr int kRec = kRing2 ? kLapStride : 8;
+  constexpr uint32_t kLocB = 2 * kRec;
+  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
+  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
+  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
+  if (lb >= nblocks) return;
+  const int64_t tile = lb / a.nchunks;
+  const int chunk = (int)(lb - tile * a.nchunks);
+  const int W = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int32_t* inf = a.info + 4 * tile;
+  const int32_t seg0 = ld_uniform(inf), run0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
+  const int32_t seg1 = ld_uniform(inf + 4), run1 = ld_uniform(inf + 5);
+  const int k0 = chunk * a.KL;
+  const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
+  const uint32_t colB = (uint32_t)a.KL * kCin * (uint32_t)sizeof(S);    // LDS column stride
+  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
+  const uint32_t data_off = loc_off + (uint32_t)nnodes * kLocB;
+  uint32_t ctr = 0;
+  // copy: table rows of the tile's nodes, then the stencil columns
+  {
+    uint32_t tn = 0;
+    for (int32_t r = run0; r < run1; ++r) {
+      const int32_t first = ld_uniform(a.runs + 2 * r), cnt = ld_uniform(a.runs + 2 * r + 1);
+      dma_copy(static_cast<const char*>(a.coef) + (size_t)first * kCoefB, lds, tn * kCoefB, (uint32_t)cnt * kCoefB,
+               wave, W, lane, ctr);
+      dma_copy(reinterpret_cast<const char*>(a.loc) + (size_t)first * kLocB, lds, loc_off + tn * kLocB,
+               (uint32_t)cnt * kLocB, wave, W, lane, ctr);
+      tn += (uint32_t)cnt;
+    }
+    const size_t gcol = (size_t)a.L * kCin * sizeof(S);                 // global column bytes
+    const char* in = static_cast<const char*>(a.in);
+    uint32_t p = 0;
+    for (int32_t sg = seg0; sg < seg1; ++sg) {
+      const int32_t first = ld_uniform(a.segs + 2 * sg), cnt = ld_uniform(a.segs + 2 * sg + 1);
+      if (a.KL == a.L) {
+        dma_copy(in + (size_t)first * gcol, lds, data_off + p * colB, (uint32_t)cnt * colB, wave, W, lane, ctr);
+      } else {
+        const uint32_t nb = (uint32_t)klc * kCin * (uint32_t)sizeof(S);
+        for (int32_t c = 0; c < cnt; ++c)
+          dma_copy(in + (size_t)(first + c) * gcol + (size_t)k0 * kCin * sizeof(S), lds, data_off + (p + c) * colB,
+                   nb, wave, W, lane, ctr);
+      }
+      p += (uint32_t)cnt;
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  // compute: node tn of the tile goes to wave tn mod W
+  uint32_t t0 = 0;
+  for (int32_t r = run0; r < run1; ++r) {
+    const int32_t first = ld_uniform(a.runs + 2 * r), cnt = ld_uniform(a.runs + 2 * r + 1);
+    for (int32_t n = (int32_t)((wave - (int)(t0 % (uint32_t)W) + W) % W); n < cnt; n += W) {
+      const uint32_t tn = t0 + (uint32_t)n;
+      const uint32_t obase = (uint32_t)(first + n) * (uint32_t)a.L + (uint32_t)k0;
+      uint32_t pos[kRec - 1], self;
+      int ne;
+      tile_positions<kRec>(lds, loc_off + tn * kLocB, pos, self, ne);
+      if constexpr (kRing2) {
+        C w[kRec - 1];
+#pragma unroll
+        for (int s = 0; s < kRec - 1; ++s) w[s] = lds_ld<C>(lds, tn * kCoefB + s * (uint32_t)sizeof(C));
+        if (ne <= 18) tile_node2<S, U, 18>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
+        else tile_node2<S, 1, kRec - 1>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
+      } else {
+        C2 cf[7];
+#pragma unroll
+        for (int s = 0; s < 7; ++s) cf[s] = lds_ld<C2>(lds, tn * kCoefB + s * (uint32_t)sizeof(C2));
+        const C2 dg = lds_ld<C2>(lds, tn * kCoefB + 7 * (uint32_t)sizeof(C2));
+        switch (ne) {
+          case 6: tile_node1<S, OP, U, 6>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+          case 5: tile_node1<S, OP, 1, 5>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+          case 7: tile_node1<S, OP, 1, 7>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+          case 4: tile_node1<S, OP, 1, 4>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+          default: tile_node1<S, OP, 1, 3>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        }
+      }
+    }
+    t0 += (uint32_t)cnt;
+  }
+}
+
 // ---- conservation: fixed-order FP64 sums of V_i div_ik --------------------------
 //
 // Workgroup b reduces nodes [b*chunk, (b+1)*chunk) for every level.  Wave w
@@ -783,6 +1017,32 @@ hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int n
   return hipGetLastError();
 }
 
+template <class S, int OP>
+hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds, int64_t nblocks, int remap,
+                         hipStream_t st) {
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_tile<S, OP, 1>), g, b, lds, st, a, nblocks, remap); break;
+    case 2: hipLaunchKernelGGL((k_tile<S, OP, 2>), g, b, lds, st, a, nblocks, remap); break;
+    default: hipLaunchKernelGGL((k_tile<S, OP, 3>), g, b, lds, st, a, nblocks, remap); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_tiles_t(int op, const TileArgs& a, int U, uint32_t lds, const Shape& sh, hipStream_t st) {
+  const int64_t nblocks = a.ntiles * a.nchunks;
+  const int64_t grid = sh.xcd_remap ? (nblocks + 7) / 8 * 8 : nblocks;
+  const dim3 g((unsigned)grid), b((unsigned)(64 * sh.waves_per_block));
+  switch (op) {
+    case OP_GRAD: return launch_tile_u<S, OP_GRAD>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_DIV: return launch_tile_u<S, OP_DIV>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_GRADT: return launch_tile_u<S, OP_GRADT>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_DIVT: return launch_tile_u<S, OP_DIVT>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_LAP: return launch_tile_u<S, OP_LAP>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 bool uses_window(int op, int nlev, const Shape& sh) {
@@ -835,6 +1095,69 @@ hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord
     case DT_F64: return launch_op_t<double>(op, a, U, nblocks, window, shape, stream);
     case DT_F32: return launch_op_t<float>(op, a, U, nblocks, window, shape, stream);
     case DT_BF16: return launch_op_t<bf16_t>(op, a, U, nblocks, window, shape, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
+  return (dtype == DT_F32 || dtype == DT_F64) && nlev > 32 && sh.lds_tiles == 1;
+}
+
+TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
+  TileGeom g;
+  const int64_t es = dtype == DT_F64 ? 8 : 4;
+  const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
+  g.ring = op == OP_LAP ? 2 : 1;
+  g.row_bytes = g.ring == 2 ? kLapStride * (es + 2) : 8 * 2 * es + 16;
+  g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
+  // Column chunk: whole columns if a tile of `want` columns (and half as many
+  // nodes' table rows) fits, else the largest equal chunks that do; if even
+  // that fails, fall back to the minimum of one node's stencil.
+  const int64_t stencil = g.ring == 2 ? kLapStride : 8;
+  const int64_t wants[2] = {g.ring == 2 ? 96 : 48, stencil};
+  g.KL = 0;
+  for (int64_t want : wants) {
+    const int64_t per_col = (g.budget - (want / 2) * g.row_bytes) / want;
+    const int64_t kl = per_col / (cin * es);
+    if (kl < 1) continue;
+    const int64_t nch = (nlev + kl - 1) / kl;
+    g.KL = (int)((nlev + nch - 1) / nch);
+    break;
+  }
+  if (g.KL < 1) return g;   // no tile geometry fits the budget
+  g.nchunks = (nlev + g.KL - 1) / g.KL;
+  g.col_bytes = (int64_t)g.KL * cin * es;
+  return g;
+}
+
+hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
+                        void* out, const Shape& shape, hipStream_t stream) {
+  // the tiling's LDS footprint must be the one the kernel lays out
+  const int64_t es = dtype == DT_F64 ? 8 : 4;
+  const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
+  const int64_t row = op == OP_LAP ? kLapStride * (es + 2) : 8 * 2 * es + 16;
+  if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || dt.lds_bytes > 65536 ||
+      dt.col_bytes != (int64_t)dt.KL * cin * es || dt.row_bytes != row)
+    return hipErrorInvalidValue;
+  TileArgs a;
+  a.info = dt.info;
+  a.segs = dt.segs;
+  a.runs = dt.runs;
+  a.loc = dt.loc;
+  a.coef = op == OP_LAP ? t.lap_w : t.coef[op];
+  a.in = in;
+  a.out = out;
+  a.ntiles = dt.ntiles;
+  a.L = nlev;
+  a.KL = dt.KL;
+  a.nchunks = dt.nchunks;
+  a.nt = nt_of(shape) ? 1 : 0;
+  const int nsl = (dt.KL + 63) / 64;
+  int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
+  if (U > nsl) U = nsl;
+  switch (dtype) {
+    case DT_F64: return launch_tiles_t<double>(op, a, U, dt.lds_bytes, shape, stream);
+    case DT_F32: return launch_tiles_t<float>(op, a, U, dt.lds_bytes, shape, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -31,11 +31,14 @@ struct Shape {
   int run_nodes = 0;         // 0: kDefaultRunNodes (kDefaultWindowRunNodes on the row-window walk)
   int nt_stores = 0;         // 0: default (off), 1: non-temporal output stores, 2: off
   int row_window = 0;        // 0: default (on), 1: on, 2: off -- row-window walk of 1-ring operators
+  int lds_tiles = 0;         // 0: default (off), 1: on, 2: off -- LDS tile path (FP32/FP64, > 32 levels)
+  int tile_kb = 0;           // 0: kDefaultTileKB; LDS budget of one tile in KiB (8..64)
 };
 
 constexpr int kDefaultBandRows = 32;
 constexpr int kDefaultRunNodes = 16;
 constexpr int kDefaultWindowRunNodes = 64;
+constexpr int kDefaultTileKB = 48;
 inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
 inline int run_nodes_of(const Shape& s) { return s.run_nodes > 0 ? s.run_nodes : kDefaultRunNodes; }
 inline bool nt_of(const Shape& s) { return s.nt_stores == 1; }
@@ -58,6 +61,28 @@ int lanes_per_node(int nlev, const Shape& sh);
 int slices_per_iter(int nlev, const Shape& sh);
 // Level slices (of 64) in flight per node step, row-window path (1..3).
 int window_slices(int nlev, const Shape& sh);
+
+// LDS tile path: device tiles of one tiling (see HaloTiles in mesh.hpp).
+struct DevTiles {
+  const int32_t* info = nullptr;
+  const int32_t* segs = nullptr;
+  const int32_t* runs = nullptr;
+  const uint16_t* loc = nullptr;
+  int64_t ntiles = 0;
+  int KL = 0, nchunks = 1;  // level chunk of the launch (set per call)
+  uint32_t lds_bytes = 0;   // largest tile footprint
+  int64_t col_bytes = 0, row_bytes = 0;   // LDS bytes per column chunk / node the tiling was cut for
+};
+// Geometry of a tiled launch: stencil ring, level chunking (KL levels per
+// chunk), LDS bytes per column chunk and per node (table rows), budget.
+struct TileGeom {
+  int ring = 1, KL = 0, nchunks = 1;   // KL = 0: no geometry fits the budget
+  int64_t col_bytes = 0, row_bytes = 0, budget = 0;
+};
+bool uses_tiles(int op, int dtype, int nlev, const Shape& sh);
+TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh);
+hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
+                        void* out, const Shape& shape, hipStream_t stream);
 
 // Single-field operator launch; in/out are device pointers of the dtype and
 // `ord` the device node order work follows.

@@ -89,4 +89,33 @@ void build_band_runs(const HostMesh& m, int band_rows, int run_nodes, std::vecto
 // slot of the neighbour table above the degree: deg | meta << 8.
 int window_meta(const HostMesh& m, int64_t i, int deg);
 
+// LDS tiles.  A tile is a set of nodes (runs of consecutive nodes taken in
+// the band order) together with every column its stencils read: the one-ring
+// (ring 1) or two-ring (ring 2) entries of each node and the node itself.
+// The sorted column set is stored as segments of consecutive nodes, so a
+// workgroup copies it from HBM with contiguous loads; column c of the set
+// (in ascending node order) sits at position c of the tile's LDS buffer.
+// loc[i][s] is the LDS position of entry s of node i (padded with the
+// node's own position), and the last entry packs the node's own position
+// with its entry count: pos | count << kLocCountShift.
+constexpr int kLocCountShift = 11;
+constexpr int kMaxTileCols = (1 << kLocCountShift) - 1;
+
+struct HaloTiles {
+  int ring = 1;
+  int stride = 8;                  // loc entries per node: 8 (ring 1) or kLapStride (ring 2)
+  int64_t ntiles = 0;
+  std::vector<int32_t> info;       // [ntiles + 1][4]: first segment, first run, columns, nodes
+  std::vector<int32_t> segs;       // [nseg][2]: first node, count
+  std::vector<int32_t> runs;       // [nrun][2]: first node, count (the tile's own nodes)
+  std::vector<uint16_t> loc;       // [V][stride]
+  int max_cols = 0, max_nodes = 0; // largest tile
+};
+
+// Cut the band order into tiles whose LDS footprint, columns * col_bytes +
+// nodes * row_bytes, stays within budget_bytes (and at most kMaxTileCols
+// columns).  Throws std::runtime_error when a single node does not fit.
+void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_rows, int run_nodes,
+                      int64_t col_bytes, int64_t row_bytes, int64_t budget_bytes, HaloTiles& out);
+
 }  // namespace atlasnabla

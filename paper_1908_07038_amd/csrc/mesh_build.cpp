@@ -578,4 +578,111 @@ void build_band_order(const HostMesh& m, int band_rows, int run_nodes, std::vect
   }
 }
 
+void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_rows, int run_nodes,
+                      int64_t col_bytes, int64_t row_bytes, int64_t budget_bytes, HaloTiles& out) {
+  if (ring != 1 && ring != 2) throw std::runtime_error("ring must be 1 or 2");
+  if (col_bytes <= 0 || row_bytes < 0 || budget_bytes <= 0) throw std::runtime_error("bad tile byte sizes");
+  const int64_t V = m.V;
+  const int stride = ring == 1 ? kEll : t.lap_stride;
+  out = HaloTiles();
+  out.ring = ring;
+  out.stride = stride;
+  out.loc.assign((size_t)V * stride, 0);
+  std::vector<int32_t> runs;
+  build_band_runs(m, band_rows, run_nodes, runs);
+
+  // entries of node i (without i itself)
+  auto entries = [&](int64_t i, int32_t* e) -> int {
+    if (ring == 1) {
+      const int deg = t.nbr8[kEll * i + kEll - 1] & 0xff;
+      for (int s = 0; s < deg; ++s) e[s] = t.nbr8[kEll * i + s];
+      return deg;
+    }
+    const int cnt = t.lap_nbr[(size_t)stride * i + stride - 1];
+    for (int s = 0; s < cnt; ++s) e[s] = t.lap_nbr[(size_t)stride * i + s];
+    return cnt;
+  };
+
+  std::vector<int64_t> stamp(V, -1);     // tile that already holds column v
+  std::vector<int32_t> cols, nodes;      // current tile
+  int64_t tile = 0;
+  int32_t e[kLapStride];
+
+  auto close_tile = [&]() {
+    if (nodes.empty()) return;
+    std::sort(cols.begin(), cols.end());
+    const int32_t seg0 = (int32_t)(out.segs.size() / 2), run0 = (int32_t)(out.runs.size() / 2);
+    out.info.push_back(seg0);
+    out.info.push_back(run0);
+    out.info.push_back((int32_t)cols.size());
+    out.info.push_back((int32_t)nodes.size());
+    for (size_t c = 0; c < cols.size(); ++c) {
+      if (c > 0 && cols[c] == cols[c - 1] + 1) {
+        ++out.segs.back();
+      } else {
+        out.segs.push_back(cols[c]);
+        out.segs.push_back(1);
+      }
+    }
+    for (size_t q = 0; q < nodes.size(); ++q) {
+      if (q > 0 && nodes[q] == nodes[q - 1] + 1) {
+        ++out.runs.back();
+      } else {
+        out.runs.push_back(nodes[q]);
+        out.runs.push_back(1);
+      }
+    }
+    auto pos = [&](int32_t v) -> uint16_t {
+      return (uint16_t)(std::lower_bound(cols.begin(), cols.end(), v) - cols.begin());
+    };
+    int32_t ce[kLapStride];
+    for (int32_t i : nodes) {
+      const int n = entries(i, ce);
+      const uint16_t self = pos(i);
+      uint16_t* l = &out.loc[(size_t)stride * i];
+      for (int s = 0; s < stride - 1; ++s) l[s] = s < n ? pos(ce[s]) : self;
+      l[stride - 1] = (uint16_t)(self | (n << kLocCountShift));
+    }
+    out.max_cols = std::max(out.max_cols, (int)cols.size());
+    out.max_nodes = std::max(out.max_nodes, (int)nodes.size());
+    cols.clear();
+    nodes.clear();
+    ++tile;
+  };
+
+  for (size_t r = 0; r < runs.size(); r += 2) {
+    for (int32_t q = 0; q < runs[r + 1]; ++q) {
+      const int32_t i = runs[r] + q;
+      const int n = entries(i, e);
+      e[n] = i;
+      int fresh = 0;
+      for (int s = 0; s <= n; ++s) {
+        bool dup = stamp[e[s]] == tile;
+        for (int u = 0; u < s && !dup; ++u) dup = e[u] == e[s];
+        fresh += !dup;
+      }
+      const int64_t need = (int64_t)(cols.size() + fresh) * col_bytes + (int64_t)(nodes.size() + 1) * row_bytes;
+      if (!nodes.empty() && (need > budget_bytes || (int64_t)cols.size() + fresh > kMaxTileCols)) {
+        close_tile();
+        fresh = n + 1;   // every entry of a node is distinct
+      }
+      if ((int64_t)fresh * col_bytes + row_bytes > budget_bytes || fresh > kMaxTileCols)
+        throw std::runtime_error("one node's stencil does not fit the LDS tile budget");
+      for (int s = 0; s <= n; ++s)
+        if (stamp[e[s]] != tile) {
+          stamp[e[s]] = tile;
+          cols.push_back(e[s]);
+        }
+      nodes.push_back(i);
+    }
+  }
+  close_tile();
+  out.ntiles = tile;
+  // sentinel: one past the last tile
+  out.info.push_back((int32_t)(out.segs.size() / 2));
+  out.info.push_back((int32_t)(out.runs.size() / 2));
+  out.info.push_back(0);
+  out.info.push_back(0);
+}
+
 }  // namespace atlasnabla

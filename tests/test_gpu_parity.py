@@ -86,6 +86,27 @@ def test_parity(name, N, L, dtype):
         print(f"  bf16 kernel-only {err:.2e} total {total:.2e}")
 
 
+TILE_CODES = {torch.float64: pa.F64, torch.float32: pa.F32}
+OP_BITS = {"gradient": pa.OP_GRADIENT, "divergence": pa.OP_DIVERGENCE, "laplacian": pa.OP_LAPLACIAN,
+           "gradient_adjoint": pa.OP_GRADIENT_ADJOINT, "divergence_adjoint": pa.OP_DIVERGENCE_ADJOINT}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", list(OPS))
+@pytest.mark.parametrize("N,L,kb", [(32, 137, 0), (32, 33, 8), (2, 70, 64), (32, 200, 16)])
+def test_parity_lds_tiles(name, N, L, kb, dtype):
+    """The LDS tile path against the oracle (whole columns and level chunks)."""
+    print(f"case tiles {name} O{N} x {L} kb {kb} {dtype}", flush=True)
+    M = gpu_mesh(N)
+    pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], dict(lds_tiles=1, tile_kb=kb))
+    try:
+        y, ref, _, _, _ = _run(name, N, L, dtype)
+    finally:
+        pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], None)
+    err = rel(y, ref)
+    assert err <= TOL[dtype], (name, N, L, dtype, err)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_config_o32(dtype):
     """O32 x 10: SH sum to degree 10 with scale 1 + 0.1 k; grad, div(grad f), lap."""
@@ -169,13 +190,17 @@ def test_dot_product_identities(dtype):
     V, L = M.nnodes, 91
     x = torch.from_numpy(W.normal((V, L), 1)).to(DEV).to(dtype)
     y = torch.from_numpy(W.normal((V, L, 2), 2)).to(DEV).to(dtype)
+    # scale of the rounding: ||G x|| ||y|| (Cauchy-Schwarz), not the
+    # cancelling sum itself
     tol = 1e-13 if dtype == torch.float64 else 1e-5
-    lhs = (pa.gradient(M, x).double() * y.double()).sum().item()
+    gx = pa.gradient(M, x).double()
+    lhs = (gx * y.double()).sum().item()
     rhs = (x.double() * pa.gradient_adjoint(M, y).double()).sum().item()
-    assert abs(lhs - rhs) <= tol * abs(lhs)
-    lhs = (pa.divergence(M, y).double() * x.double()).sum().item()
+    assert abs(lhs - rhs) <= tol * (gx.norm() * y.double().norm()).item()
+    dy = pa.divergence(M, y).double()
+    lhs = (dy * x.double()).sum().item()
     rhs = (y.double() * pa.divergence_adjoint(M, x).double()).sum().item()
-    assert abs(lhs - rhs) <= tol * abs(lhs)
+    assert abs(lhs - rhs) <= tol * (dy.norm() * x.double().norm()).item()
 
 
 def test_autograd_gradcheck():
@@ -205,14 +230,19 @@ def test_argument_errors():
 
 SHAPES = [dict(lanes_per_node=p, slices_per_iter=u, waves_per_block=w, nodes_per_wave=n, xcd_remap=x,
                band_rows=h, run_nodes=r, nt_stores=nt, row_window=rw)
-          for (p, u, w, n, x, h, r, nt, rw, nw) in [
-              (16, 1, 1, 1, 2, 1, 1, 1, 2, 0), (16, 3, 4, 2, 1, 0, 0, 2, 2, 0),
-              (32, 2, 2, 4, 1, 7, 3, 1, 2, 0), (64, 3, 4, 8, 2, 64, 64, 2, 2, 0),
-              (64, 1, 1, 3, 1, 1000, 5, 1, 2, 0), (32, 3, 4, 1, 2, 2, 1000, 2, 2, 0),
-              (0, 1, 1, 1, 2, 1, 1, 1, 1, 1), (0, 3, 4, 2, 1, 0, 0, 2, 1, 2),
-              (0, 2, 2, 4, 1, 7, 3, 1, 1, 1), (0, 3, 4, 8, 2, 64, 64, 2, 0, 2),
-              (0, 1, 1, 3, 1, 1000, 5, 1, 1, 2), (0, 2, 4, 1, 2, 2, 1000, 2, 1, 1),
-              (0, 3, 2, 3, 1, 5, 7, 2, 1, 2), (0, 1, 4, 1, 1, 3, 2, 2, 0, 1)]]
+          for (p, u, w, n, x, h, r, nt, rw) in [(16, 1, 1, 1, 2, 1, 1, 1, 2), (16, 3, 4, 2, 1, 0, 0, 2, 2),
+                                                (32, 2, 2, 4, 1, 7, 3, 1, 2), (64, 3, 4, 8, 2, 64, 64, 2, 2),
+                                                (64, 1, 1, 3, 1, 1000, 5, 1, 2), (32, 3, 4, 1, 2, 2, 1000, 2, 2),
+                                                (0, 1, 1, 1, 2, 1, 1, 1, 1), (0, 3, 4, 2, 1, 0, 0, 2, 1),
+                                                (0, 2, 2, 4, 1, 7, 3, 1, 1), (0, 3, 4, 8, 2, 64, 64, 2, 0),
+                                                (0, 1, 1, 3, 1, 1000, 5, 1, 1), (0, 2, 4, 1, 2, 2, 1000, 2, 1)]]
+# LDS tiles (FP32/FP64 only; other dtypes ignore the switch): budgets that
+# force whole columns, level chunks and tiny tiles, every wave count
+SHAPES += [dict(lds_tiles=1, tile_kb=kb, waves_per_block=w, slices_per_iter=u, band_rows=h, run_nodes=r,
+                xcd_remap=x, nt_stores=nt)
+           for (kb, w, u, h, r, x, nt) in [(0, 4, 0, 0, 0, 0, 0), (64, 2, 3, 32, 16, 1, 2), (8, 1, 1, 1, 1, 2, 1),
+                                           (24, 4, 2, 4, 8, 1, 1), (16, 2, 3, 1000, 1000, 2, 2),
+                                           (40, 1, 2, 7, 3, 1, 2)]]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
