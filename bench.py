@@ -39,9 +39,16 @@ OP_ELEMS = {"gradient": (1, 2), "divergence": (2, 1), "laplacian": (1, 1),
             "gradient_adjoint": (2, 1), "divergence_adjoint": (1, 2), "conservation": (1, 0)}
 OP_SWEEPS = {"gradient": 1, "divergence": 1, "laplacian": 2, "gradient_adjoint": 1,
              "divergence_adjoint": 1, "conservation": 0}
-KERNEL_NAME = {"gradient": "k_op<float, 0, U>", "divergence": "k_op<float, 1, U>",
-               "gradient_adjoint": "k_op<float, 2, U>", "divergence_adjoint": "k_op<float, 3, U>",
-               "laplacian": "k_op<float, 4, U>", "conservation": "k_cons_partial<float> + k_cons_final"}
+CONSERVATION_KERNELS = "k_cons_partial + k_cons_final"
+
+
+def kernel_names(pa, mesh, dtype_code, L):
+    """Kernel each operator runs with the mesh's current (default) shapes."""
+    bits = {"gradient": pa.OP_GRADIENT, "divergence": pa.OP_DIVERGENCE, "laplacian": pa.OP_LAPLACIAN,
+            "gradient_adjoint": pa.OP_GRADIENT_ADJOINT, "divergence_adjoint": pa.OP_DIVERGENCE_ADJOINT}
+    names = {op: pa.describe(mesh, b, dtype_code, L)[1] for op, b in bits.items()}
+    names["conservation"] = CONSERVATION_KERNELS
+    return names
 
 
 def log(*a):
@@ -149,6 +156,9 @@ def run_gpu(args):
             r = refs[k]
             err[k] = float(f"{(torch.linalg.vector_norm((v.double() - r).flatten()) / torch.linalg.vector_norm(r.flatten())).item():.3g}")
         sweeps = sum(OP_SWEEPS.values())
+        codes = {"f64": pa.F64, "f32": pa.F32, "bf16": pa.BF16}
+        for op, name in kernel_names(pa, mesh, codes[dname], L).items():
+            per_op[op]["kernel"] = name
         results[dname] = {"ms_per_step": round(t_step * 1e3, 4),
                           "edge_updates_s": float(f"{sweeps * E * L / t_step:.4g}"),
                           "per_op": per_op, "rel_l2_vs_f64": err, "conservation_max_rel": cons}
@@ -227,7 +237,7 @@ def main():
     dms = f32["per_op"][dom]["ms"]
     dbytes = alg_bytes(dom, V, L, 4)
     traffic = measured_traffic(dom, "f32")
-    roof = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "op": dom,
+    roof = {"bound": "hbm", "kernel": f32["per_op"][dom]["kernel"], "op": dom,
             "achieved": round(dbytes / (dms * 1e-3) / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(dbytes / (dms * 1e-3) / HBM_PEAK, 4),
             "alg_bytes_per_launch": dbytes,

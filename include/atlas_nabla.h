@@ -211,9 +211,11 @@ typedef struct {
   int32_t slices_per_iter;  /* level slices in flight per lane, 1..3         */
   int32_t band_rows;        /* rows per band of the node processing order:
                                runs of a band are visited by longitude so
-                               rows above and below stay in cache            */
+                               rows above and below stay in cache (default
+                               32); LDS tiles: rows per tile (default 4)      */
   int32_t run_nodes;        /* consecutive nodes of a row per run (default 16,
-                               64 on the row-window walk)                     */
+                               64 on the row-window walk); LDS tiles: bands
+                               swept together by longitude (default 8)        */
   int32_t nt_stores;        /* 1: non-temporal output stores, 2: plain (the
                                default)                                      */
   int32_t row_window;       /* 1-ring operators on columns of more than 32
@@ -221,9 +223,16 @@ typedef struct {
                                node's column loads (the default), 2 gather
                                every slot per node                            */
   int32_t lds_tiles;        /* FP32/FP64 columns of more than 32 levels:
-                               1 stage each tile of nodes and the columns its
-                               stencils read in LDS, 0/2 off (the default)    */
+                               stage tiles of nodes with the columns their
+                               stencils read in LDS: 1 persistent workgroups,
+                               double buffered; 3 one tile per workgroup;
+                               0/2 off (the default)                          */
   int32_t tile_kb;          /* LDS budget of one tile in KiB, 8..64 (0: 48)  */
+  int32_t tile_waves;       /* persistent tiles: computing waves, 1..7 (0: 6) */
+  int32_t producer_waves;   /* persistent tiles: copying waves, 1..4 (0: 2);
+                               tile_waves + producer_waves <= 8               */
+  int32_t tile_wgs_per_cu;  /* persistent tiles: workgroups per CU, 1..4
+                               (0: 1); two tile buffers each must fit LDS     */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;
@@ -274,6 +283,15 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
  * work plus one device allocation of 4 bytes per node). */
 int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op,
                          const atlas_tune_t* tune);
+
+/* Describe the launch a single-field call of (op, dtype) on nlev levels
+ * would make with the mesh's current shape: the shape after per-operator
+ * defaults are applied (to *resolved, if not NULL) and the name of the
+ * kernel it runs, e.g. "k_tile<float, 0, 3>" (to kernel, NUL-terminated and
+ * truncated to len bytes, if not NULL).  Works on host-only meshes; no
+ * device work, no allocation. */
+int atlas_nabla_describe(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
+                         atlas_tune_t* resolved, char* kernel, int32_t len);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,9 @@ class TuneShape(ctypes.Structure):
                 ("lanes_per_node", ctypes.c_int32), ("slices_per_iter", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32), ("run_nodes", ctypes.c_int32),
                 ("nt_stores", ctypes.c_int32), ("row_window", ctypes.c_int32),
-                ("lds_tiles", ctypes.c_int32), ("tile_kb", ctypes.c_int32)]
+                ("lds_tiles", ctypes.c_int32), ("tile_kb", ctypes.c_int32),
+                ("tile_waves", ctypes.c_int32), ("producer_waves", ctypes.c_int32),
+                ("tile_wgs_per_cu", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -88,6 +90,8 @@ _SIGS = {
     "atlas_nabla_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, _I32, _P, _P, _I32, _P,
                                         ctypes.POINTER(TuneShape), ctypes.POINTER(ctypes.c_float)]),
     "atlas_nabla_set_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(TuneShape)]),
+    "atlas_nabla_describe": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, _I32, ctypes.POINTER(TuneShape),
+                                            ctypes.c_char_p, _I32]),
 }
 
 
@@ -309,6 +313,14 @@ def tune(mesh, op, x, out, reps=10):
                                   ctypes.c_void_p(out.data_ptr()), reps, _stream(x), ctypes.byref(best),
                                   ctypes.byref(ms)))
     return best.as_dict(), ms.value
+
+
+def describe(mesh, op, dtype_code, nlev):
+    """(resolved shape dict, kernel name) of a single-field call of op."""
+    sh = TuneShape()
+    buf = ctypes.create_string_buffer(128)
+    _check(lib().atlas_nabla_describe(mesh.handle, dtype_code, op, nlev, ctypes.byref(sh), buf, 128))
+    return sh.as_dict(), buf.value.decode()
 
 
 def set_tune(mesh, op, dtype_code, shape=None):

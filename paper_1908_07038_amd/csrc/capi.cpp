@@ -118,19 +118,24 @@ struct atlas_mesh_s {
 
   // Device tiles of an LDS-tiled launch, built and uploaded on first use.
   DevTiles tiles(const TileGeom& g, const Shape& sh) {
-    const std::vector<int64_t> key = {g.ring, band_rows_of(sh), run_nodes_of(sh), g.col_bytes, g.row_bytes, g.budget};
+    const int h = sh.band_rows > 0 ? sh.band_rows : kDefaultTileRows;
+    const int sweep = sh.run_nodes > 0 ? sh.run_nodes : kDefaultTileSweep;
+    const std::vector<int64_t> key = {g.ring, h, sweep, g.col_bytes, g.row_bytes, g.budget};
     std::lock_guard<std::mutex> lk(order_mu);
     auto it = tilings.find(key);
     if (it != tilings.end()) return it->second;
     HaloTiles ht;
-    build_halo_tiles(host, host_nbr, g.ring, band_rows_of(sh), run_nodes_of(sh), g.col_bytes, g.row_bytes,
-                     g.budget, ht);
+    build_halo_tiles(host, host_nbr, g.ring, h, sweep, g.col_bytes, g.row_bytes, g.budget, ht);
     DevTiles dt;
+    // eight pairs of padding: kernels fetch pairs eight at a time
+    ht.segs.resize(ht.segs.size() + 16, 0);
+    ht.runs.resize(ht.runs.size() + 16, 0);
     dt.info = upload(ht.info);
     dt.segs = upload(ht.segs);
     dt.runs = upload(ht.runs);
     dt.loc = upload(ht.loc);
     dt.ntiles = ht.ntiles;
+    dt.max_nodes = ht.max_nodes;
     dt.col_bytes = g.col_bytes;
     dt.row_bytes = g.row_bytes;
     int64_t lds = 0;
@@ -218,6 +223,9 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->row_window = s.row_window;
   t->lds_tiles = s.lds_tiles;
   t->tile_kb = s.tile_kb;
+  t->tile_waves = s.tile_waves;
+  t->producer_waves = s.producer_waves;
+  t->tile_wgs_per_cu = s.tile_wgs_per_cu;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -250,10 +258,18 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.nt_stores = t->nt_stores;
   if (t->row_window < 0 || t->row_window > 2) return fail(ATLAS_EINVAL, "row_window must be 0, 1 or 2");
   s.row_window = t->row_window;
-  if (t->lds_tiles < 0 || t->lds_tiles > 2) return fail(ATLAS_EINVAL, "lds_tiles must be 0, 1 or 2");
+  if (t->lds_tiles < 0 || t->lds_tiles > 3) return fail(ATLAS_EINVAL, "lds_tiles must be 0..3");
   s.lds_tiles = t->lds_tiles;
   if (t->tile_kb != 0 && (t->tile_kb < 8 || t->tile_kb > 64)) return fail(ATLAS_EINVAL, "tile_kb must be 0 or 8..64");
   s.tile_kb = t->tile_kb;
+  if (t->tile_waves < 0 || t->tile_waves > 7) return fail(ATLAS_EINVAL, "tile_waves must be 0..7");
+  if (t->producer_waves < 0 || t->producer_waves > 4) return fail(ATLAS_EINVAL, "producer_waves must be 0..4");
+  if ((t->tile_waves ? t->tile_waves : 6) + (t->producer_waves ? t->producer_waves : 2) > 8)
+    return fail(ATLAS_EINVAL, "tile_waves + producer_waves must be at most 8");
+  s.tile_waves = t->tile_waves;
+  s.producer_waves = t->producer_waves;
+  if (t->tile_wgs_per_cu < 0 || t->tile_wgs_per_cu > 4) return fail(ATLAS_EINVAL, "tile_wgs_per_cu must be 0..4");
+  s.tile_wgs_per_cu = t->tile_wgs_per_cu;
 
   return ATLAS_OK;
 }
@@ -275,7 +291,7 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   if (overlaps(in, nin, out, nout)) return fail(ATLAS_EINVAL, "output overlaps input");
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
-  Shape sh = shape_override ? *shape_override : mesh->shape[op][dtype];
+  Shape sh = resolve_shape(op, dtype, nlev, shape_override ? *shape_override : mesh->shape[op][dtype]);
   const TileGeom tg = uses_tiles(op, dtype, nlev, sh) ? tile_geom(op, dtype, nlev, sh) : TileGeom();
   if (tg.KL > 0) {   // tiles asked for and a tile geometry fits the budget
     DevTiles dt;
@@ -289,7 +305,8 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
     } catch (const std::exception& ex) {
       return fail(ATLAS_EHIP, ex.what());
     }
-    hipError_t e = launch_tiles(op, dtype, mesh->tables(dtype), dt, nlev, in, out, sh, (hipStream_t)stream);
+    hipError_t e =
+        launch_tiles(op, dtype, mesh->tables(dtype), dt, nlev, in, out, sh, mesh->num_cus, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, kOpName[op]);
     return ATLAS_OK;
   }
@@ -520,6 +537,20 @@ int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op, const atlas_
   return ATLAS_OK;
 }
 
+int atlas_nabla_describe(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, atlas_tune_t* resolved, char* kernel,
+                         int32_t len) {
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  if (!dtype_size(dtype)) return fail(ATLAS_EDTYPE, "unknown dtype");
+  const int o = op_from_bit(op);
+  if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit");
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  if (kernel && len <= 0) return fail(ATLAS_EINVAL, "len must be positive");
+  const Shape sh = resolve_shape(o, dtype, nlev, mesh->shape[o][dtype]);
+  if (resolved) shape_out(sh, resolved);
+  if (kernel) kernel_label(o, dtype, nlev, sh, kernel, len);
+  return ATLAS_OK;
+}
+
 int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, const void* in, void* out, int32_t reps,
                      void* stream, atlas_tune_t* best, float* best_ms) {
   int rc = check_mesh_device(mesh);
@@ -557,11 +588,14 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
     }
     return ATLAS_OK;
   };
-  // stage 1: column mapping (row-window walk, or lanes per node) and slices per iteration
+  // stage 1: the default, then each path -- row-window walk, gather with P
+  // lanes per node, LDS tiles -- with its main parameters
   {
+    if ((rc = time_shape(Shape()))) goto done;
     for (int u = 1; u <= 3; ++u) {
-      if (!uses_window(o, nlev, Shape())) break;
       Shape s;
+      s.lds_tiles = 2;
+      if (!uses_window(o, nlev, s)) break;
       s.slices_per_iter = u;
       if ((rc = time_shape(s))) goto done;
     }
@@ -570,12 +604,51 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
       if (nlev <= 32 && p != 16) continue;   // short columns always use nlev lanes
       for (int u = 1; u <= 3; ++u) {
         Shape s;
+        s.lds_tiles = 2;
         s.row_window = 2;
         s.lanes_per_node = nlev <= 32 ? 0 : p;
         s.slices_per_iter = u;
         if ((rc = time_shape(s))) goto done;
       }
     }
+    Shape probe;
+    probe.lds_tiles = 3;
+    if (uses_tiles(o, dtype, nlev, probe)) {
+      const int kbs[] = {32, 48, 64};
+      for (int kb : kbs)
+        for (int h = 2; h <= 4; ++h) {
+          Shape s;
+          s.lds_tiles = 3;
+          s.tile_kb = kb;
+          s.band_rows = h;
+          if ((rc = time_shape(s))) goto done;
+        }
+      for (int kb = 48; kb <= 64; kb += 16)
+        for (int h = 3; h <= 5; ++h)
+          for (int pw = 2; pw <= 3; ++pw) {
+            Shape s;
+            s.lds_tiles = 1;
+            s.tile_kb = kb;
+            s.band_rows = h;
+            s.producer_waves = pw;
+            s.tile_waves = 8 - pw;
+            if ((rc = time_shape(s))) goto done;
+          }
+    }
+  }
+  if (bs.lds_tiles == 1 || bs.lds_tiles == 3 || (bs.lds_tiles == 0 && uses_tiles(o, dtype, nlev,
+                                                                                 resolve_shape(o, dtype, nlev, bs)))) {
+    // LDS tiles won: bands swept together
+    const Shape base = resolve_shape(o, dtype, nlev, bs);
+    const int sweeps[] = {4, 8, 16};
+    for (int b : sweeps) {
+      Shape s = base;
+      s.run_nodes = b;
+      if ((rc = time_shape(s))) goto done;
+    }
+    shape_out(bs, best);
+    if (best_ms) *best_ms = bestt;
+    goto done;
   }
   // stage 2: workgroup shape and XCD remapping around the best mapping
   {

@@ -31,6 +31,7 @@
 // contiguous part of the order (whole bands) in its own L2.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -639,19 +640,79 @@ constexpr int kLocCountShift = 11;
 
 typedef __attribute__((address_space(3))) void* lds_vptr;
 
+// s_waitcnt immediate with lgkmcnt = 0 and vmcnt, expcnt left at their
+// maxima (vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).  Issued
+// through the builtin rather than inline assembly so that the compiler's own
+// wait insertion accounts for it.
+constexpr int kWaitLgkm0 = 0xC07F;
+
+constexpr uint64_t kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
+
 // Direct loads of nbytes (a multiple of 4) from global src to LDS byte offset
-// dst.  Instruction q of the copy (64 dwords, lane l moves dword 64 q + l)
-// goes to wave (ctr + q) mod W, ctr counting the instructions of the earlier
-// copies of the workgroup, so that small copies spread over the waves.
+// dst: 16 bytes per lane (lane l of instruction q moves bytes 16 (64 q + l)
+// onwards; gfx950 accepts any 4-byte alignment on both sides), then the last
+// 0..3 dwords one per lane.  Instruction q goes to wave (ctr + q) mod W, ctr
+// counting the instructions of the workgroup's earlier copies, so that small
+// copies spread over the waves.
 __device__ __forceinline__ void dma_copy(const char* src, char* lds, uint32_t dst, uint32_t nbytes, int wave, int W,
                                          int lane, uint32_t& ctr) {
-  const uint32_t ndw = nbytes >> 2;
-  const uint32_t ninst = (ndw + 63) >> 6;
+  const uint32_t n16 = nbytes >> 4;
+  const uint32_t ninst = (n16 + 63) >> 6;
   for (uint32_t q = (uint32_t)((wave - (int)(ctr % (uint32_t)W) + W) % W); q < ninst; q += (uint32_t)W) {
     const uint32_t d = q * 64 + (uint32_t)lane;
-    if (d < ndw) __builtin_amdgcn_global_load_lds(src + 4 * (size_t)d, (lds_vptr)(lds + dst + 256 * q), 4, 0, 0);
+    if (d < n16)
+      __builtin_amdgcn_global_load_lds(src + 16 * (size_t)d, (lds_vptr)(lds + dst + 1024 * q), 16, 0, 0);
   }
   ctr += ninst;
+  const uint32_t rem = (nbytes & 15u) >> 2;
+  if (rem) {
+    if ((uint32_t)wave == ctr % (uint32_t)W && (uint32_t)lane < rem)
+      __builtin_amdgcn_global_load_lds(src + 16 * (size_t)n16 + 4 * lane, (lds_vptr)(lds + dst + 16 * n16), 4, 0, 0);
+    ++ctr;
+  }
+}
+
+// Direct loads of cnt column chunks of nb bytes each (nb a multiple of 4),
+// chunk c at global src + c * gstride, packed back to back at LDS byte offset
+// dst.  The LDS image is contiguous, so each instruction still fills 64
+// consecutive units (16 bytes when nb allows, else 4); a lane finds its
+// chunk by dividing its unit index by the units per chunk.
+__device__ __forceinline__ void dma_copy_strided(const char* src, size_t gstride, uint32_t cnt, uint32_t nb,
+                                                 char* lds, uint32_t dst, int wave, int W, int lane,
+                                                 uint32_t& ctr) {
+  const bool wide = (nb & 15u) == 0;
+  const uint32_t ub = wide ? 16u : 4u;
+  const uint32_t upc = nb / ub;                       // units per chunk
+  const uint32_t total = cnt * upc;
+  const uint32_t ninst = (total + 63) >> 6;
+  for (uint32_t q = (uint32_t)((wave - (int)(ctr % (uint32_t)W) + W) % W); q < ninst; q += (uint32_t)W) {
+    const uint32_t u = q * 64 + (uint32_t)lane;
+    if (u < total) {
+      const uint32_t c = u / upc, o = u - c * upc;
+      const char* g = src + (size_t)c * gstride + (size_t)o * ub;
+      if (wide) __builtin_amdgcn_global_load_lds(g, (lds_vptr)(lds + dst + 1024 * q), 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds(g, (lds_vptr)(lds + dst + 256 * q), 4, 0, 0);
+    }
+  }
+  ctr += ninst;
+}
+
+// Calls f(first, count) for pairs [b, e) of a (first, count) table, in order.
+// Pairs come eight at a time from independent scalar loads (one wait per
+// eight); the tables carry eight pairs of padding so the loads stay in
+// bounds.  Scalar loads leave the vector memory counter alone, so fetching
+// the next pairs never waits for direct loads already in flight.
+template <class F>
+__device__ __forceinline__ void for_pairs(const int32_t* tab, int32_t b, int32_t e, F&& f) {
+  for (int32_t base = b; base < e; base += 8) {
+    int32_t v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = ld_uniform(tab + 2 * (size_t)base + j);
+    const int32_t n = e - base;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < n) f(v[2 * q], v[2 * q + 1]);
+  }
 }
 
 template <class T>
@@ -771,43 +832,37 @@ __global__ __launch_bounds__(256) void k_tile(TileArgs a, int64_t nblocks, int r
   const int32_t seg1 = ld_uniform(inf + 4), run1 = ld_uniform(inf + 5);
   const int k0 = chunk * a.KL;
   const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
-  const uint32_t colB = (uint32_t)a.KL * kCin * (uint32_t)sizeof(S);    // LDS column stride
+  const uint32_t colB = (uint32_t)klc * kCin * (uint32_t)sizeof(S);     // LDS column stride (this chunk)
   const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
   const uint32_t data_off = loc_off + (uint32_t)nnodes * kLocB;
   uint32_t ctr = 0;
   // copy: table rows of the tile's nodes, then the stencil columns
   {
     uint32_t tn = 0;
-    for (int32_t r = run0; r < run1; ++r) {
-      const int32_t first = ld_uniform(a.runs + 2 * r), cnt = ld_uniform(a.runs + 2 * r + 1);
+    for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
       dma_copy(static_cast<const char*>(a.coef) + (size_t)first * kCoefB, lds, tn * kCoefB, (uint32_t)cnt * kCoefB,
                wave, W, lane, ctr);
       dma_copy(reinterpret_cast<const char*>(a.loc) + (size_t)first * kLocB, lds, loc_off + tn * kLocB,
                (uint32_t)cnt * kLocB, wave, W, lane, ctr);
       tn += (uint32_t)cnt;
-    }
+    });
     const size_t gcol = (size_t)a.L * kCin * sizeof(S);                 // global column bytes
     const char* in = static_cast<const char*>(a.in);
     uint32_t p = 0;
-    for (int32_t sg = seg0; sg < seg1; ++sg) {
-      const int32_t first = ld_uniform(a.segs + 2 * sg), cnt = ld_uniform(a.segs + 2 * sg + 1);
-      if (a.KL == a.L) {
+    for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
+      if (a.KL == a.L)
         dma_copy(in + (size_t)first * gcol, lds, data_off + p * colB, (uint32_t)cnt * colB, wave, W, lane, ctr);
-      } else {
-        const uint32_t nb = (uint32_t)klc * kCin * (uint32_t)sizeof(S);
-        for (int32_t c = 0; c < cnt; ++c)
-          dma_copy(in + (size_t)(first + c) * gcol + (size_t)k0 * kCin * sizeof(S), lds, data_off + (p + c) * colB,
-                   nb, wave, W, lane, ctr);
-      }
+      else
+        dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * kCin * sizeof(S), gcol, (uint32_t)cnt, colB, lds,
+                         data_off + p * colB, wave, W, lane, ctr);
       p += (uint32_t)cnt;
-    }
+    });
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   // compute: node tn of the tile goes to wave tn mod W
   uint32_t t0 = 0;
-  for (int32_t r = run0; r < run1; ++r) {
-    const int32_t first = ld_uniform(a.runs + 2 * r), cnt = ld_uniform(a.runs + 2 * r + 1);
+  for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
     for (int32_t n = (int32_t)((wave - (int)(t0 % (uint32_t)W) + W) % W); n < cnt; n += W) {
       const uint32_t tn = t0 + (uint32_t)n;
       const uint32_t obase = (uint32_t)(first + n) * (uint32_t)a.L + (uint32_t)k0;
@@ -835,6 +890,229 @@ __global__ __launch_bounds__(256) void k_tile(TileArgs a, int64_t nblocks, int r
       }
     }
     t0 += (uint32_t)cnt;
+  });
+}
+
+// ---- persistent LDS tiles, double buffered ------------------------------------
+//
+// One or two workgroups per CU stay resident and walk their share of the
+// tiles.  Producer waves copy tile n+1 into one LDS buffer (direct loads, then
+// their own wait) while consumer waves evaluate tile n from the other; one
+// barrier per tile swaps the buffers.  Consumers use the lane mapping of the
+// gather path: P lanes per node, 64 / P nodes per wave step, lane t handling
+// levels t, t + P, ...; each lane reads its node's LDS positions and
+// coefficients from the tile's table rows in LDS (broadcast reads).  The
+// producers also store the tile's node indices into LDS.
+
+__device__ __forceinline__ void tile_issue(const TileArgs& a, int64_t lb, char* buf, uint32_t kCoefB, uint32_t kLocB,
+                                           int kCin, uint32_t es, int pw, int NP, int lane) {
+  const int64_t tile = lb / a.nchunks;
+  const int chunk = (int)(lb - tile * a.nchunks);
+  const int32_t* inf = a.info + 4 * tile;
+  const int32_t seg0 = ld_uniform(inf), run0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
+  const int32_t seg1 = ld_uniform(inf + 4), run1 = ld_uniform(inf + 5);
+  const int k0 = chunk * a.KL;
+  const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
+  const uint32_t colB = (uint32_t)klc * kCin * es;   // LDS column stride (this chunk)
+  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
+  const uint32_t ids_off = loc_off + (uint32_t)nnodes * kLocB;
+  const uint32_t data_off = ids_off + (((uint32_t)nnodes * 4u + 15u) & ~15u);
+  uint32_t ctr = 0, tn = 0;
+  for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
+    dma_copy(static_cast<const char*>(a.coef) + (size_t)first * kCoefB, buf, tn * kCoefB, (uint32_t)cnt * kCoefB, pw,
+             NP, lane, ctr);
+    dma_copy(reinterpret_cast<const char*>(a.loc) + (size_t)first * kLocB, buf, loc_off + tn * kLocB,
+             (uint32_t)cnt * kLocB, pw, NP, lane, ctr);
+    for (int32_t n = pw * 64 + lane; n < cnt; n += NP * 64)
+      *reinterpret_cast<int32_t*>(buf + ids_off + 4 * (tn + (uint32_t)n)) = first + n;
+    tn += (uint32_t)cnt;
+  });
+  const size_t gcol = (size_t)a.L * kCin * es;
+  const char* in = static_cast<const char*>(a.in);
+  uint32_t p = 0;
+  for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
+    if (a.KL == a.L)
+      dma_copy(in + (size_t)first * gcol, buf, data_off + p * colB, (uint32_t)cnt * colB, pw, NP, lane, ctr);
+    else
+      dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * kCin * es, gcol, (uint32_t)cnt, colB, buf,
+                       data_off + p * colB, pw, NP, lane, ctr);
+    p += (uint32_t)cnt;
+  });
+}
+
+// P-lane evaluation of 1-ring nodes from an LDS tile: NS slots (7 = padded
+// with the node itself and zero coefficients).
+template <class S, int OP, int NS, int U>
+__device__ __forceinline__ void tile_lanes1(const TileArgs& a, const char* buf, uint32_t data_off, uint32_t colB,
+                                            const uint32_t* so, uint32_t xo, const typename Traits<S>::C2* cf,
+                                            typename Traits<S>::C2 dg, uint32_t obase, bool ok, int t, int P,
+                                            int klc) {
+  using C = typename Traits<S>::C;
+  using X = typename WinT<S, OP>::X;
+  S* __restrict__ out = static_cast<S*>(a.out);
+  const int nsl = (klc + P - 1) / P;
+  for (int r0 = 0; r0 < nsl; r0 += U) {
+    X v[U][NS], x0[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = t + P * (r0 + u);
+      st[u] = ok && k < klc;
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(X);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_ld<X>(buf, so[s] + kk);
+      x0[u] = lds_ld<X>(buf, xo + kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      win_emit<S, OP, NS>(out, obase + (uint32_t)(t + P * (r0 + u)), st[u], a.nt, x0[u], v[u], cf, dg);
+  }
+}
+
+template <class S, int NS, int U>
+__device__ __forceinline__ void tile_lanes2(const TileArgs& a, const char* buf, const uint32_t* so, uint32_t xo,
+                                            const typename Traits<S>::C* w, uint32_t obase, bool ok, int t, int P,
+                                            int klc) {
+  using C = typename Traits<S>::C;
+  S* __restrict__ out = static_cast<S*>(a.out);
+  const int nsl = (klc + P - 1) / P;
+  for (int r0 = 0; r0 < nsl; r0 += U) {
+    C v[U][NS], x0[U];
+    bool st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = t + P * (r0 + u);
+      st[u] = ok && k < klc;
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(C);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_ld<C>(buf, so[s] + kk);
+      x0[u] = lds_ld<C>(buf, xo + kk);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      C acc = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc = fma(w[s], v[u][s] - x0[u], acc);
+      if (st[u]) {
+        const uint32_t o = obase + (uint32_t)(t + P * (r0 + u));
+        if (a.nt) st1<true>(out + (size_t)o, acc);
+        else st1<false>(out + (size_t)o, acc);
+      }
+    }
+  }
+}
+
+template <class S, int OP, int U>
+__device__ __forceinline__ void tile_consume(const TileArgs& a, int64_t lb, const char* buf, int cw, int NC, int P,
+                                             int lane) {
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  constexpr bool kRing2 = OP == OP_LAP;
+  constexpr int kRec = kRing2 ? kLapStride : 8;
+  constexpr uint32_t kLocB = 2 * kRec;
+  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
+  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
+  const int64_t tile = lb / a.nchunks;
+  const int chunk = (int)(lb - tile * a.nchunks);
+  const int32_t nnodes = ld_uniform(a.info + 4 * tile + 3);
+  const int k0 = chunk * a.KL;
+  const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
+  const uint32_t colB = (uint32_t)klc * kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
+  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
+  const uint32_t ids_off = loc_off + (uint32_t)nnodes * kLocB;
+  const uint32_t data_off = ids_off + (((uint32_t)nnodes * 4u + 15u) & ~15u);
+  const int G = 64 / P;
+  const int j = lane / P, t = lane - (lane / P) * P;
+  for (int32_t tn0 = cw * G; tn0 < nnodes; tn0 += NC * G) {
+    const int32_t tn = tn0 + j;
+    const bool ok = j < G && tn < nnodes;
+    const uint32_t tq = (uint32_t)(ok ? tn : tn0);
+    const int32_t i = lds_ld<int32_t>(buf, ids_off + 4 * tq);
+    const uint32_t obase = (uint32_t)i * (uint32_t)a.L + (uint32_t)k0;
+    uint32_t w32[kRec / 2];
+#pragma unroll
+    for (int q = 0; q < kRec / 8; ++q) {
+      const uint4 r = lds_ld<uint4>(buf, loc_off + tq * kLocB + 16 * q);
+      w32[4 * q] = r.x;
+      w32[4 * q + 1] = r.y;
+      w32[4 * q + 2] = r.z;
+      w32[4 * q + 3] = r.w;
+    }
+    uint32_t so[kRec - 1];
+#pragma unroll
+    for (int s = 0; s < kRec - 1; ++s) so[s] = data_off + ((s & 1) ? (w32[s >> 1] >> 16) : (w32[s >> 1] & 0xffffu)) * colB;
+    const uint32_t last = w32[kRec / 2 - 1] >> 16;
+    const uint32_t xo = data_off + (last & ((1u << kLocCountShift) - 1)) * colB;
+    const int ne = (int)(last >> kLocCountShift);
+    if constexpr (kRing2) {
+      C w[kRec - 1];
+#pragma unroll
+      for (int s = 0; s < kRec - 1; ++s) w[s] = lds_ld<C>(buf, tq * kCoefB + s * (uint32_t)sizeof(C));
+      if (__all(ne <= 18)) tile_lanes2<S, 18, U>(a, buf, so, xo, w, obase, ok, t, P, klc);
+      else tile_lanes2<S, kRec - 1, 1>(a, buf, so, xo, w, obase, ok, t, P, klc);
+    } else {
+      C2 cf[7];
+#pragma unroll
+      for (int s = 0; s < 7; ++s) cf[s] = lds_ld<C2>(buf, tq * kCoefB + s * (uint32_t)sizeof(C2));
+      const C2 dg = lds_ld<C2>(buf, tq * kCoefB + 7 * (uint32_t)sizeof(C2));
+      if (__all(ne == 6)) tile_lanes1<S, OP, 6, U>(a, buf, data_off, colB, so, xo, cf, dg, obase, ok, t, P, klc);
+      else tile_lanes1<S, OP, 7, 1>(a, buf, data_off, colB, so, xo, cf, dg, obase, ok, t, P, klc);
+    }
+  }
+}
+
+template <class S, int OP, int U>
+__global__ __launch_bounds__(512) void k_tile2(TileArgs a, int64_t nblocks, int remap, uint32_t buf_bytes, int nprod,
+                                               int P) {
+  extern __shared__ __align__(16) char lds[];
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  constexpr bool kRing2 = OP == OP_LAP;
+  constexpr int kRec = kRing2 ? kLapStride : 8;
+  constexpr uint32_t kLocB = 2 * kRec;
+  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
+  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
+  const int W = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  // this workgroup's tiles: with remapping, the workgroups of one XCD sweep
+  // a contiguous eighth of the tile list together
+  const int64_t nwg = gridDim.x, b = blockIdx.x;
+  int64_t lb, step, end;
+  if (remap) {
+    const int64_t per = (nblocks + 7) / 8;
+    lb = (b % 8) * per + b / 8;
+    step = nwg / 8;
+    end = (b % 8 + 1) * per < nblocks ? (b % 8 + 1) * per : nblocks;
+  } else {
+    lb = b;
+    step = nwg;
+    end = nblocks;
+  }
+  const bool producer = wave < nprod;
+  uint32_t cur = 0;
+  if (producer && lb < end) {
+    tile_issue(a, lb, lds, kCoefB, kLocB, kCin, (uint32_t)sizeof(S), wave, nprod, lane);
+    __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
+  }
+  __syncthreads();
+  while (lb < end) {
+    const int64_t nx = lb + step;
+    if (producer) {
+      if (nx < end) {
+        tile_issue(a, nx, lds + (cur ^ buf_bytes), kCoefB, kLocB, kCin, (uint32_t)sizeof(S), wave, nprod, lane);
+        __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
+      }
+    } else {
+      tile_consume<S, OP, U>(a, lb, lds + cur, wave - nprod, W - nprod, P, lane);
+    }
+    // LDS traffic of this step done (consumer reads, producer index stores;
+    // the producers' direct loads were waited for above); consumers' global
+    // stores may stay in flight across the barrier
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_s_barrier();
+    lb = nx;
+    cur ^= buf_bytes;
   }
 }
 
@@ -1028,6 +1306,43 @@ hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds,
   return hipGetLastError();
 }
 
+template <class S, int OP>
+hipError_t launch_tile2_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t buf_bytes, int64_t nblocks, int remap,
+                          int nprod, int P, hipStream_t st) {
+  const uint32_t lds = 2 * buf_bytes;
+  const void* fn = U == 1 ? reinterpret_cast<const void*>(&k_tile2<S, OP, 1>)
+                   : U == 2 ? reinterpret_cast<const void*>(&k_tile2<S, OP, 2>)
+                            : reinterpret_cast<const void*>(&k_tile2<S, OP, 3>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_tile2<S, OP, 1>), g, b, lds, st, a, nblocks, remap, buf_bytes, nprod, P); break;
+    case 2: hipLaunchKernelGGL((k_tile2<S, OP, 2>), g, b, lds, st, a, nblocks, remap, buf_bytes, nprod, P); break;
+    default: hipLaunchKernelGGL((k_tile2<S, OP, 3>), g, b, lds, st, a, nblocks, remap, buf_bytes, nprod, P); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_tiles2_t(int op, const TileArgs& a, int U, uint32_t buf_bytes, int nprod, int ncons, int per_cu,
+                           int num_cus, int P, const Shape& sh, hipStream_t st) {
+  const int64_t nblocks = a.ntiles * a.nchunks;
+  int64_t grid = (int64_t)per_cu * num_cus;
+  if (grid > nblocks) grid = nblocks;
+  const int remap = (sh.xcd_remap && grid % 8 == 0) ? 1 : 0;
+  const dim3 g((unsigned)grid), b((unsigned)(64 * (nprod + ncons)));
+  switch (op) {
+    case OP_GRAD: return launch_tile2_u<S, OP_GRAD>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    case OP_DIV: return launch_tile2_u<S, OP_DIV>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    case OP_GRADT: return launch_tile2_u<S, OP_GRADT>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    case OP_DIVT: return launch_tile2_u<S, OP_DIVT>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    case OP_LAP: return launch_tile2_u<S, OP_LAP>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class S>
 hipError_t launch_tiles_t(int op, const TileArgs& a, int U, uint32_t lds, const Shape& sh, hipStream_t st) {
   const int64_t nblocks = a.ntiles * a.nchunks;
@@ -1099,8 +1414,33 @@ hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord
   }
 }
 
+Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
+  Shape e = sh;
+  if (e.lds_tiles != 0) return e;
+  if ((dtype != DT_F32 && dtype != DT_F64) || nlev <= 32) {
+    e.lds_tiles = 2;
+    return e;
+  }
+  // Measured defaults at O1280 x 137 (rows: mode, KiB, tile rows, computing
+  // and copying waves of the persistent form): scalar-input 1-ring operators,
+  // vector-input ones, the two-ring Laplacian.
+  struct Def { int mode, kb, rows, cw, pw; };
+  const bool vec_in = op == OP_DIV || op == OP_GRADT;
+  Def d;
+  if (dtype == DT_F32) d = op == OP_LAP ? Def{1, 64, 5, 5, 3} : vec_in ? Def{3, 64, 4, 0, 0} : Def{3, 32, 2, 0, 0};
+  else d = op == OP_LAP ? Def{3, 48, 4, 0, 0} : vec_in ? Def{2, 0, 0, 0, 0} : Def{1, 64, 3, 5, 3};
+  e.lds_tiles = d.mode;
+  if (d.mode == 2) return e;
+  if (!e.tile_kb) e.tile_kb = d.kb;
+  if (!e.band_rows) e.band_rows = d.rows;
+  if (!e.tile_waves) e.tile_waves = d.cw;
+  if (!e.producer_waves) e.producer_waves = d.pw;
+  return e;
+}
+
 bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
-  return (dtype == DT_F32 || dtype == DT_F64) && nlev > 32 && sh.lds_tiles == 1;
+  (void)op;
+  return (dtype == DT_F32 || dtype == DT_F64) && nlev > 32 && (sh.lds_tiles == 1 || sh.lds_tiles == 3);
 }
 
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
@@ -1120,8 +1460,12 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
     const int64_t per_col = (g.budget - (want / 2) * g.row_bytes) / want;
     const int64_t kl = per_col / (cin * es);
     if (kl < 1) continue;
+    // equal chunks, rounded up to whole 16-byte units when that still fits
     const int64_t nch = (nlev + kl - 1) / kl;
-    g.KL = (int)((nlev + nch - 1) / nch);
+    const int64_t m = 16 / (cin * es) > 1 ? 16 / (cin * es) : 1;
+    int64_t k = (nlev + nch - 1) / nch;
+    if ((k + m - 1) / m * m <= kl) k = (k + m - 1) / m * m;
+    g.KL = (int)(k < nlev ? k : nlev);
     break;
   }
   if (g.KL < 1) return g;   // no tile geometry fits the budget
@@ -1131,7 +1475,7 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
 }
 
 hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
-                        void* out, const Shape& shape, hipStream_t stream) {
+                        void* out, const Shape& shape, int num_cus, hipStream_t stream) {
   // the tiling's LDS footprint must be the one the kernel lays out
   const int64_t es = dtype == DT_F64 ? 8 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
@@ -1152,14 +1496,60 @@ hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& d
   a.KL = dt.KL;
   a.nchunks = dt.nchunks;
   a.nt = nt_of(shape) ? 1 : 0;
-  const int nsl = (dt.KL + 63) / 64;
+  if (shape.lds_tiles == 3) {
+    const int nsl = (dt.KL + 63) / 64;
+    int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
+    if (U > nsl) U = nsl;
+    switch (dtype) {
+      case DT_F64: return launch_tiles_t<double>(op, a, U, dt.lds_bytes, shape, stream);
+      case DT_F32: return launch_tiles_t<float>(op, a, U, dt.lds_bytes, shape, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  // persistent double-buffered form
+  const int nprod = shape.producer_waves > 0 ? shape.producer_waves : 2;
+  const int ncons = shape.tile_waves > 0 ? shape.tile_waves : 6;
+  if (nprod + ncons > 8) return hipErrorInvalidValue;
+  const uint32_t buf_bytes = (dt.lds_bytes + (((uint32_t)dt.max_nodes * 4u + 15u) & ~15u) + 15u) & ~15u;
+  // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
+  int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;
+  while (per_cu > 1 && (uint64_t)2 * buf_bytes * per_cu > kLdsPerCu) --per_cu;
+  if ((uint64_t)2 * buf_bytes > kLdsPerCu) return hipErrorInvalidValue;
+  const int P = lanes_per_node(dt.KL, shape);
+  const int nsl = (dt.KL + P - 1) / P;
   int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
   if (U > nsl) U = nsl;
   switch (dtype) {
-    case DT_F64: return launch_tiles_t<double>(op, a, U, dt.lds_bytes, shape, stream);
-    case DT_F32: return launch_tiles_t<float>(op, a, U, dt.lds_bytes, shape, stream);
+    case DT_F64: return launch_tiles2_t<double>(op, a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
+    case DT_F32: return launch_tiles2_t<float>(op, a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+void kernel_label(int op, int dtype, int nlev, const Shape& sh, char* buf, int len) {
+  const char* ty = dtype == DT_F64 ? "double" : dtype == DT_F32 ? "float" : "unsigned short";
+  const char* name = nullptr;
+  int U = 1;
+  if (uses_tiles(op, dtype, nlev, sh)) {
+    const TileGeom g = tile_geom(op, dtype, nlev, sh);
+    if (g.KL > 0) {
+      const int P = sh.lds_tiles == 3 ? 64 : lanes_per_node(g.KL, sh);
+      const int nsl = (g.KL + P - 1) / P;
+      U = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
+      if (U > nsl) U = nsl;
+      name = sh.lds_tiles == 3 ? "k_tile" : "k_tile2";
+    }
+  }
+  if (!name) {
+    if (op != OP_LAP && uses_window(op, nlev, sh)) {
+      name = "k_win";
+      U = window_slices(nlev, sh);
+    } else {
+      name = "k_op";
+      U = slices_per_iter(nlev, sh);
+    }
+  }
+  snprintf(buf, (size_t)len, "%s<%s, %d, %d>", name, ty, op, U);
 }
 
 int window_slices(int nlev, const Shape& sh) {

@@ -31,14 +31,21 @@ struct Shape {
   int run_nodes = 0;         // 0: kDefaultRunNodes (kDefaultWindowRunNodes on the row-window walk)
   int nt_stores = 0;         // 0: default (off), 1: non-temporal output stores, 2: off
   int row_window = 0;        // 0: default (on), 1: on, 2: off -- row-window walk of 1-ring operators
-  int lds_tiles = 0;         // 0: default (off), 1: on, 2: off -- LDS tile path (FP32/FP64, > 32 levels)
+  int lds_tiles = 0;         // 0: default (per operator and dtype, see resolve_shape), 1: on
+                             // (persistent, double buffered), 2: off, 3: on (one tile per
+                             // workgroup) -- LDS tile path (FP32/FP64, > 32 levels)
   int tile_kb = 0;           // 0: kDefaultTileKB; LDS budget of one tile in KiB (8..64)
+  int tile_waves = 0;        // 0: 6; consumer waves per persistent tile workgroup
+  int producer_waves = 0;    // 0: 2; producer (copy) waves per persistent tile workgroup
+  int tile_wgs_per_cu = 0;   // 0: 1; persistent tile workgroups per CU
 };
 
 constexpr int kDefaultBandRows = 32;
 constexpr int kDefaultRunNodes = 16;
 constexpr int kDefaultWindowRunNodes = 64;
 constexpr int kDefaultTileKB = 48;
+constexpr int kDefaultTileRows = 4;    // LDS tiles: rows per tile (band_rows)
+constexpr int kDefaultTileSweep = 8;   // LDS tiles: bands swept together (run_nodes)
 inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
 inline int run_nodes_of(const Shape& s) { return s.run_nodes > 0 ? s.run_nodes : kDefaultRunNodes; }
 inline bool nt_of(const Shape& s) { return s.nt_stores == 1; }
@@ -71,6 +78,7 @@ struct DevTiles {
   int64_t ntiles = 0;
   int KL = 0, nchunks = 1;  // level chunk of the launch (set per call)
   uint32_t lds_bytes = 0;   // largest tile footprint
+  int32_t max_nodes = 0;    // most nodes in a tile
   int64_t col_bytes = 0, row_bytes = 0;   // LDS bytes per column chunk / node the tiling was cut for
 };
 // Geometry of a tiled launch: stencil ring, level chunking (KL levels per
@@ -79,10 +87,16 @@ struct TileGeom {
   int ring = 1, KL = 0, nchunks = 1;   // KL = 0: no geometry fits the budget
   int64_t col_bytes = 0, row_bytes = 0, budget = 0;
 };
+// The shape a launch runs with: lds_tiles = 0 picks the path (and tile
+// parameters left at 0) from per-operator, per-dtype defaults.
+Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh);
 bool uses_tiles(int op, int dtype, int nlev, const Shape& sh);
+// Name of the kernel template instance a single-field launch with the
+// resolved shape runs, e.g. "k_tile<float, 0, 3>".
+void kernel_label(int op, int dtype, int nlev, const Shape& resolved, char* buf, int len);
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh);
 hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
-                        void* out, const Shape& shape, hipStream_t stream);
+                        void* out, const Shape& shape, int num_cus, hipStream_t stream);
 
 // Single-field operator launch; in/out are device pointers of the dtype and
 // `ord` the device node order work follows.

@@ -89,9 +89,10 @@ void build_band_runs(const HostMesh& m, int band_rows, int run_nodes, std::vecto
 // slot of the neighbour table above the degree: deg | meta << 8.
 int window_meta(const HostMesh& m, int64_t i, int deg);
 
-// LDS tiles.  A tile is a set of nodes (runs of consecutive nodes taken in
-// the band order) together with every column its stencils read: the one-ring
-// (ring 1) or two-ring (ring 2) entries of each node and the node itself.
+// LDS tiles.  A tile is a set of nodes (band_rows consecutive rows by one
+// longitude sector; see mesh_build.cpp) together with every column its
+// stencils read: the one-ring (ring 1) or two-ring (ring 2) entries of each
+// node and the node itself.
 // The sorted column set is stored as segments of consecutive nodes, so a
 // workgroup copies it from HBM with contiguous loads; column c of the set
 // (in ascending node order) sits at position c of the tile's LDS buffer.
@@ -112,9 +113,11 @@ struct HaloTiles {
   int max_cols = 0, max_nodes = 0; // largest tile
 };
 
-// Cut the band order into tiles whose LDS footprint, columns * col_bytes +
+// Cut the mesh into tiles of band_rows rows by one longitude sector, swept
+// run_nodes bands at a time, whose LDS footprint, columns * col_bytes +
 // nodes * row_bytes, stays within budget_bytes (and at most kMaxTileCols
-// columns).  Throws std::runtime_error when a single node does not fit.
+// columns); a sector tile that does not fit is split row-major.  Throws
+// std::runtime_error when a single node does not fit.
 void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_rows, int run_nodes,
                       int64_t col_bytes, int64_t row_bytes, int64_t budget_bytes, HaloTiles& out);
 

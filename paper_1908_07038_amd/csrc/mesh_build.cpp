@@ -588,8 +588,40 @@ void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_r
   out.ring = ring;
   out.stride = stride;
   out.loc.assign((size_t)V * stride, 0);
-  std::vector<int32_t> runs;
-  build_band_runs(m, band_rows, run_nodes, runs);
+  if (band_rows < 1 || run_nodes < 1) throw std::runtime_error("tile rows and bands per sweep must be >= 1");
+
+  // Candidate tiles: `band_rows` rows by one longitude sector.  Rows are
+  // grouped into bands of band_rows rows and bands into sweeps of run_nodes
+  // bands; a sweep is cut into S sectors of equal longitude, sector s of row
+  // k holding nodes j in [ceil(s n_k / S), ceil((s + 1) n_k / S)).  S is set
+  // so that a tile of the sweep's longest rows fits the budget.  Order:
+  // sweep, sector, band -- tiles stacked in latitude follow each other, so
+  // the halo rows they share are still in L2.
+  std::vector<int32_t> gnodes;
+  std::vector<int64_t> gstart;
+  {
+    const int h = band_rows, r = ring;
+    for (int K0 = 0; K0 < m.nrows; K0 += h * run_nodes) {
+      const int K1 = std::min(m.nrows, K0 + h * run_nodes);
+      int64_t nmax = 1;
+      for (int k = K0; k < K1; ++k) nmax = std::max<int64_t>(nmax, m.row_size[k]);
+      const int64_t hh = h + 2 * r;
+      int64_t w = (budget_bytes - hh * (2 + r) * col_bytes) / (hh * col_bytes + (int64_t)h * row_bytes);
+      if (w < 1) w = 1;
+      const int64_t S = (nmax + w - 1) / w;
+      for (int64_t sct = 0; sct < S; ++sct)
+        for (int b0 = K0; b0 < K1; b0 += h) {
+          gstart.push_back((int64_t)gnodes.size());
+          for (int k = b0; k < std::min(b0 + h, K1); ++k) {
+            const int64_t n = m.row_size[k];
+            const int64_t j0 = (sct * n + S - 1) / S, j1 = ((sct + 1) * n + S - 1) / S;
+            for (int64_t j = j0; j < j1; ++j) gnodes.push_back((int32_t)(m.row_off[k] + j));
+          }
+          if ((int64_t)gnodes.size() == gstart.back()) gstart.pop_back();
+        }
+    }
+    gstart.push_back((int64_t)gnodes.size());
+  }
 
   // entries of node i (without i itself)
   auto entries = [&](int64_t i, int32_t* e) -> int {
@@ -650,9 +682,10 @@ void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_r
     ++tile;
   };
 
-  for (size_t r = 0; r < runs.size(); r += 2) {
-    for (int32_t q = 0; q < runs[r + 1]; ++q) {
-      const int32_t i = runs[r] + q;
+  for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+    close_tile();   // a candidate tile never shares a tile with another
+    for (int64_t q = gstart[g]; q < gstart[g + 1]; ++q) {
+      const int32_t i = gnodes[q];
       const int n = entries(i, e);
       e[n] = i;
       int fresh = 0;

@@ -10,7 +10,7 @@
 // and it emulates the tiled evaluation of the gradient (ring 1) or the
 // two-ring Laplacian (ring 2) from the positions, which must equal a direct
 // gather over the neighbour tables bit for bit.
-// Usage: halo_tiles_check N nlev band_rows run_nodes ring col_bytes row_bytes budget
+// Usage: halo_tiles_check N nlev tile_rows sweep_bands ring col_bytes row_bytes budget
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -24,7 +24,7 @@ using namespace atlasnabla;
 
 int main(int argc, char** argv) {
   if (argc != 9) {
-    std::fprintf(stderr, "usage: %s N nlev band_rows run_nodes ring col_bytes row_bytes budget\n", argv[0]);
+    std::fprintf(stderr, "usage: %s N nlev tile_rows sweep_bands ring col_bytes row_bytes budget\n", argv[0]);
     return 2;
   }
   const int N = std::atoi(argv[1]), L = std::atoi(argv[2]), H = std::atoi(argv[3]), R = std::atoi(argv[4]);

@@ -109,3 +109,30 @@ def test_no_device_is_reported():
     with pytest.raises(pa.AtlasError) as e:
         pa.Mesh("O4", device=0)
     assert e.value.code == -4
+
+
+def test_describe_resolves_the_default_paths():
+    """The launch a call would make, without a device: per-operator default
+    paths for FP32/FP64 columns of more than 32 levels, the row-window walk
+    or the gather otherwise, and an explicit shape overriding the default."""
+    M = pa.Mesh("O8", device=-1)
+    cases = [(pa.OP_GRADIENT, pa.F32, 137, "k_tile<float, 0, 3>"),
+             (pa.OP_DIVERGENCE_ADJOINT, pa.F32, 137, "k_tile<float, 3, 3>"),
+             (pa.OP_DIVERGENCE, pa.F32, 137, "k_tile<float, 1, 3>"),
+             (pa.OP_LAPLACIAN, pa.F32, 137, "k_tile2<float, 4, 3>"),
+             (pa.OP_GRADIENT, pa.F64, 137, "k_tile2<double, 0, 3>"),
+             (pa.OP_DIVERGENCE, pa.F64, 137, "k_win<double, 1, 3>"),
+             (pa.OP_GRADIENT, pa.BF16, 137, "k_win<unsigned short, 0, 3>"),
+             (pa.OP_LAPLACIAN, pa.BF16, 137, "k_op<unsigned short, 4, 3>"),
+             (pa.OP_GRADIENT, pa.F32, 19, "k_op<float, 0, 1>")]
+    for op, dt, L, name in cases:
+        shape, kernel = pa.describe(M, op, dt, L)
+        assert kernel == name, (op, dt, L, kernel)
+        assert shape["lds_tiles"] in (1, 2, 3)
+    pa.set_tune(M, pa.OP_GRADIENT, pa.F32, dict(lds_tiles=2))
+    assert pa.describe(M, pa.OP_GRADIENT, pa.F32, 137)[1] == "k_win<float, 0, 3>"
+    pa.set_tune(M, pa.OP_GRADIENT, pa.F32, dict(lds_tiles=2, row_window=2, lanes_per_node=16, slices_per_iter=2))
+    assert pa.describe(M, pa.OP_GRADIENT, pa.F32, 137)[1] == "k_op<float, 0, 2>"
+    pa.set_tune(M, pa.OP_GRADIENT, pa.F32, None)
+    with pytest.raises(pa.AtlasError):
+        pa.describe(M, pa.OP_GRADIENT, pa.F32, 0)

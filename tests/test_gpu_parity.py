@@ -238,11 +238,18 @@ SHAPES = [dict(lanes_per_node=p, slices_per_iter=u, waves_per_block=w, nodes_per
                                                 (0, 1, 1, 3, 1, 1000, 5, 1, 1), (0, 2, 4, 1, 2, 2, 1000, 2, 1)]]
 # LDS tiles (FP32/FP64 only; other dtypes ignore the switch): budgets that
 # force whole columns, level chunks and tiny tiles, every wave count
-SHAPES += [dict(lds_tiles=1, tile_kb=kb, waves_per_block=w, slices_per_iter=u, band_rows=h, run_nodes=r,
+SHAPES += [dict(lds_tiles=3, tile_kb=kb, waves_per_block=w, slices_per_iter=u, band_rows=h, run_nodes=r,
                 xcd_remap=x, nt_stores=nt)
            for (kb, w, u, h, r, x, nt) in [(0, 4, 0, 0, 0, 0, 0), (64, 2, 3, 32, 16, 1, 2), (8, 1, 1, 1, 1, 2, 1),
                                            (24, 4, 2, 4, 8, 1, 1), (16, 2, 3, 1000, 1000, 2, 2),
                                            (40, 1, 2, 7, 3, 1, 2)]]
+# persistent double-buffered tiles: wave splits, workgroups per CU, lanes per node
+SHAPES += [dict(lds_tiles=1, tile_kb=kb, tile_waves=c, producer_waves=pw, tile_wgs_per_cu=g, lanes_per_node=p,
+                slices_per_iter=u, band_rows=h, run_nodes=r, xcd_remap=x, nt_stores=nt)
+           for (kb, c, pw, g, p, u, h, r, x, nt) in [(0, 0, 0, 0, 0, 0, 0, 0, 0, 0), (64, 7, 1, 1, 64, 3, 32, 16, 1, 2),
+                                                     (8, 1, 1, 4, 16, 1, 1, 1, 2, 1), (24, 4, 4, 3, 32, 2, 4, 8, 1, 1),
+                                                     (16, 2, 2, 4, 0, 3, 1000, 1000, 2, 2),
+                                                     (40, 6, 2, 2, 16, 2, 7, 3, 1, 2)]]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])

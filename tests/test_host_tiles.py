@@ -19,9 +19,9 @@ def checker():
     return exe
 
 
-# (N, nlev, band_rows, run_nodes, ring, col_bytes, row_bytes, budget): FP32 and
-# FP64 column sizes, level chunks, tiny budgets (a tile per node or two),
-# degenerate orders (one row per band, one node per run, whole rows)
+# (N, nlev, tile_rows, sweep_bands, ring, col_bytes, row_bytes, budget): FP32
+# and FP64 column sizes, level chunks, tiny budgets (a tile per node or two),
+# one-row tiles, one band per sweep, tiles taller than the mesh
 GEOMS = [(16, 70, 32, 16, 1, 280, 80, 49152), (16, 137, 4, 8, 2, 280, 240, 49152),
          (32, 137, 32, 16, 1, 548, 80, 24576), (32, 137, 32, 16, 2, 368, 144, 65536),
          (1, 5, 1, 1, 1, 40, 144, 8192), (2, 70, 32, 16, 2, 16, 240, 16384),
