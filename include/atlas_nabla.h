@@ -228,11 +228,17 @@ typedef struct {
                                double buffered; 3 one tile per workgroup;
                                0/2 off (the default)                          */
   int32_t tile_kb;          /* LDS budget of one tile in KiB, 8..64 (0: 48)  */
-  int32_t tile_waves;       /* persistent tiles: computing waves, 1..7 (0: 6) */
-  int32_t producer_waves;   /* persistent tiles: copying waves, 1..4 (0: 2);
-                               tile_waves + producer_waves <= 8               */
+  int32_t tile_waves;       /* persistent tiles: computing waves, 1..15
+                               (0: per-operator default)                      */
+  int32_t producer_waves;   /* persistent tiles: copying waves, 1..8 (0: per-
+                               operator default); tile_waves + producer_waves
+                               <= 16, and <= 8 for FP64 (launch fails else)   */
   int32_t tile_wgs_per_cu;  /* persistent tiles: workgroups per CU, 1..4
                                (0: 1); two tile buffers each must fit LDS     */
+  int32_t tile_levels;      /* LDS tiles: levels per column chunk (0: whole
+                               columns when 48 (1-ring) or 96 (two-ring)
+                               columns fit the budget, else equal chunks);
+                               ignored if one node's stencil would not fit    */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;

@@ -226,6 +226,7 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->tile_waves = s.tile_waves;
   t->producer_waves = s.producer_waves;
   t->tile_wgs_per_cu = s.tile_wgs_per_cu;
+  t->tile_levels = s.tile_levels;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -262,14 +263,16 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.lds_tiles = t->lds_tiles;
   if (t->tile_kb != 0 && (t->tile_kb < 8 || t->tile_kb > 64)) return fail(ATLAS_EINVAL, "tile_kb must be 0 or 8..64");
   s.tile_kb = t->tile_kb;
-  if (t->tile_waves < 0 || t->tile_waves > 7) return fail(ATLAS_EINVAL, "tile_waves must be 0..7");
-  if (t->producer_waves < 0 || t->producer_waves > 4) return fail(ATLAS_EINVAL, "producer_waves must be 0..4");
-  if ((t->tile_waves ? t->tile_waves : 6) + (t->producer_waves ? t->producer_waves : 2) > 8)
-    return fail(ATLAS_EINVAL, "tile_waves + producer_waves must be at most 8");
+  if (t->tile_waves < 0 || t->tile_waves > 15) return fail(ATLAS_EINVAL, "tile_waves must be 0..15");
+  if (t->producer_waves < 0 || t->producer_waves > 8) return fail(ATLAS_EINVAL, "producer_waves must be 0..8");
+  if ((t->tile_waves ? t->tile_waves : 6) + (t->producer_waves ? t->producer_waves : 2) > 16)
+    return fail(ATLAS_EINVAL, "tile_waves + producer_waves must be at most 16 (8 for FP64 launches)");
   s.tile_waves = t->tile_waves;
   s.producer_waves = t->producer_waves;
   if (t->tile_wgs_per_cu < 0 || t->tile_wgs_per_cu > 4) return fail(ATLAS_EINVAL, "tile_wgs_per_cu must be 0..4");
   s.tile_wgs_per_cu = t->tile_wgs_per_cu;
+  if (t->tile_levels < 0) return fail(ATLAS_EINVAL, "tile_levels must be >= 0");
+  s.tile_levels = t->tile_levels;
 
   return ATLAS_OK;
 }

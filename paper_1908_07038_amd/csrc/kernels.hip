@@ -1061,8 +1061,13 @@ __device__ __forceinline__ void tile_consume(const TileArgs& a, int64_t lb, cons
   }
 }
 
+// Up to 16 waves per workgroup for 4-byte data (at most 128 registers per
+// lane), 8 for FP64, whose two-ring variant needs more registers.
+template <class S>
+constexpr int kTile2Threads = sizeof(S) == 8 ? 512 : 1024;
+
 template <class S, int OP, int U>
-__global__ __launch_bounds__(512) void k_tile2(TileArgs a, int64_t nblocks, int remap, uint32_t buf_bytes, int nprod,
+__global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t nblocks, int remap, uint32_t buf_bytes, int nprod,
                                                int P) {
   extern __shared__ __align__(16) char lds[];
   using C = typename Traits<S>::C;
@@ -1427,7 +1432,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   struct Def { int mode, kb, rows, cw, pw; };
   const bool vec_in = op == OP_DIV || op == OP_GRADT;
   Def d;
-  if (dtype == DT_F32) d = op == OP_LAP ? Def{1, 64, 5, 5, 3} : vec_in ? Def{3, 64, 4, 0, 0} : Def{3, 32, 2, 0, 0};
+  if (dtype == DT_F32) d = op == OP_LAP ? Def{1, 64, 5, 12, 4} : vec_in ? Def{3, 64, 4, 0, 0} : Def{3, 32, 2, 0, 0};
   else d = op == OP_LAP ? Def{3, 48, 4, 0, 0} : vec_in ? Def{2, 0, 0, 0, 0} : Def{1, 64, 3, 5, 3};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
@@ -1456,6 +1461,16 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   const int64_t stencil = g.ring == 2 ? kLapStride : 8;
   const int64_t wants[2] = {g.ring == 2 ? 96 : 48, stencil};
   g.KL = 0;
+  if (sh.tile_levels > 0) {
+    // asked-for chunk, if one node's stencil fits with it
+    const int64_t k = sh.tile_levels < nlev ? sh.tile_levels : nlev;
+    if (stencil * k * cin * es + (stencil / 2) * g.row_bytes <= g.budget) {
+      g.KL = (int)k;
+      g.nchunks = (nlev + g.KL - 1) / g.KL;
+      g.col_bytes = (int64_t)g.KL * cin * es;
+      return g;
+    }
+  }
   for (int64_t want : wants) {
     const int64_t per_col = (g.budget - (want / 2) * g.row_bytes) / want;
     const int64_t kl = per_col / (cin * es);
@@ -1509,7 +1524,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& d
   // persistent double-buffered form
   const int nprod = shape.producer_waves > 0 ? shape.producer_waves : 2;
   const int ncons = shape.tile_waves > 0 ? shape.tile_waves : 6;
-  if (nprod + ncons > 8) return hipErrorInvalidValue;
+  if (nprod + ncons > (dtype == DT_F64 ? 8 : 16)) return hipErrorInvalidValue;
   const uint32_t buf_bytes = (dt.lds_bytes + (((uint32_t)dt.max_nodes * 4u + 15u) & ~15u) + 15u) & ~15u;
   // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
   int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;

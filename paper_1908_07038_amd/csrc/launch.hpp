@@ -38,6 +38,7 @@ struct Shape {
   int tile_waves = 0;        // 0: 6; consumer waves per persistent tile workgroup
   int producer_waves = 0;    // 0: 2; producer (copy) waves per persistent tile workgroup
   int tile_wgs_per_cu = 0;   // 0: 1; persistent tile workgroups per CU
+  int tile_levels = 0;       // 0: automatic; else levels per column chunk of a tile
 };
 
 constexpr int kDefaultBandRows = 32;
