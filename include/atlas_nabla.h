@@ -201,7 +201,8 @@ typedef struct {
 
 /* Launch shape.  Zero fields mean "library default". */
 typedef struct {
-  int32_t waves_per_block;  /* 1, 2 or 4                                    */
+  int32_t waves_per_block;  /* 1, 2, 4 or 8 (8: one-tile-per-workgroup LDS
+                               tiles only; other launches use at most 4)     */
   int32_t nodes_per_wave;   /* node groups a wave handles per workgroup       */
   int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CU count     */
   int32_t xcd_remap;        /* 1: each XCD walks a contiguous part of the
@@ -227,11 +228,14 @@ typedef struct {
                                stencils read in LDS: 1 persistent workgroups,
                                double buffered; 3 one tile per workgroup;
                                0/2 off (the default)                          */
-  int32_t tile_kb;          /* LDS budget of one tile in KiB, 8..64 (0: 48)  */
+  int32_t tile_kb;          /* LDS budget of one tile in KiB, 8..160 (0: per-
+                               operator default); the persistent form holds
+                               two tiles, which must fit the CU's 160 KiB     */
   int32_t tile_waves;       /* persistent tiles: computing waves, 1..15
                                (0: per-operator default)                      */
-  int32_t producer_waves;   /* persistent tiles: copying waves, 1..8 (0: per-
-                               operator default); tile_waves + producer_waves
+  int32_t producer_waves;   /* persistent tiles: copying waves, 1, 2, 4 or 8
+                               (0: per-operator default); tile_waves +
+                               producer_waves
                                <= 16, and <= 8 for FP64 (launch fails else)   */
   int32_t tile_wgs_per_cu;  /* persistent tiles: workgroups per CU, 1..4
                                (0: 1); two tile buffers each must fit LDS     */

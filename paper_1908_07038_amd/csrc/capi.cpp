@@ -233,7 +233,7 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   if (!t) return ATLAS_OK;
   if (t->waves_per_block) {
     const int w = t->waves_per_block;
-    if (w != 1 && w != 2 && w != 4) return fail(ATLAS_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (w != 1 && w != 2 && w != 4 && w != 8) return fail(ATLAS_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
     s.waves_per_block = w;
   }
   if (t->nodes_per_wave) {
@@ -261,10 +261,11 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.row_window = t->row_window;
   if (t->lds_tiles < 0 || t->lds_tiles > 3) return fail(ATLAS_EINVAL, "lds_tiles must be 0..3");
   s.lds_tiles = t->lds_tiles;
-  if (t->tile_kb != 0 && (t->tile_kb < 8 || t->tile_kb > 64)) return fail(ATLAS_EINVAL, "tile_kb must be 0 or 8..64");
+  if (t->tile_kb != 0 && (t->tile_kb < 8 || t->tile_kb > 160)) return fail(ATLAS_EINVAL, "tile_kb must be 0 or 8..160");
   s.tile_kb = t->tile_kb;
   if (t->tile_waves < 0 || t->tile_waves > 15) return fail(ATLAS_EINVAL, "tile_waves must be 0..15");
-  if (t->producer_waves < 0 || t->producer_waves > 8) return fail(ATLAS_EINVAL, "producer_waves must be 0..8");
+  if (t->producer_waves < 0 || t->producer_waves > 8 || (t->producer_waves & (t->producer_waves - 1)))
+    return fail(ATLAS_EINVAL, "producer_waves must be 0, 1, 2, 4 or 8");
   if ((t->tile_waves ? t->tile_waves : 6) + (t->producer_waves ? t->producer_waves : 2) > 16)
     return fail(ATLAS_EINVAL, "tile_waves + producer_waves must be at most 16 (8 for FP64 launches)");
   s.tile_waves = t->tile_waves;
@@ -626,15 +627,17 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, co
           s.band_rows = h;
           if ((rc = time_shape(s))) goto done;
         }
+      const int splits[3][2] = {{6, 2}, {4, 4}, {12, 4}};   // computing, copying waves
       for (int kb = 48; kb <= 64; kb += 16)
         for (int h = 3; h <= 5; ++h)
-          for (int pw = 2; pw <= 3; ++pw) {
+          for (const auto& sp : splits) {
+            if (dtype == ATLAS_F64 && sp[0] + sp[1] > 8) continue;
             Shape s;
             s.lds_tiles = 1;
             s.tile_kb = kb;
             s.band_rows = h;
-            s.producer_waves = pw;
-            s.tile_waves = 8 - pw;
+            s.tile_waves = sp[0];
+            s.producer_waves = sp[1];
             if ((rc = time_shape(s))) goto done;
           }
     }

@@ -651,14 +651,15 @@ constexpr uint64_t kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
 // Direct loads of nbytes (a multiple of 4) from global src to LDS byte offset
 // dst: 16 bytes per lane (lane l of instruction q moves bytes 16 (64 q + l)
 // onwards; gfx950 accepts any 4-byte alignment on both sides), then the last
-// 0..3 dwords one per lane.  Instruction q goes to wave (ctr + q) mod W, ctr
-// counting the instructions of the workgroup's earlier copies, so that small
-// copies spread over the waves.
+// 0..3 dwords one per lane.  Instruction q goes to wave (ctr + q) mod W (W a
+// power of two), ctr counting the instructions of the workgroup's earlier
+// copies, so that small copies spread over the waves.
 __device__ __forceinline__ void dma_copy(const char* src, char* lds, uint32_t dst, uint32_t nbytes, int wave, int W,
                                          int lane, uint32_t& ctr) {
   const uint32_t n16 = nbytes >> 4;
   const uint32_t ninst = (n16 + 63) >> 6;
-  for (uint32_t q = (uint32_t)((wave - (int)(ctr % (uint32_t)W) + W) % W); q < ninst; q += (uint32_t)W) {
+  const uint32_t wm = (uint32_t)W - 1;   // W is a power of two
+  for (uint32_t q = ((uint32_t)wave - ctr) & wm; q < ninst; q += (uint32_t)W) {
     const uint32_t d = q * 64 + (uint32_t)lane;
     if (d < n16)
       __builtin_amdgcn_global_load_lds(src + 16 * (size_t)d, (lds_vptr)(lds + dst + 1024 * q), 16, 0, 0);
@@ -666,7 +667,7 @@ __device__ __forceinline__ void dma_copy(const char* src, char* lds, uint32_t ds
   ctr += ninst;
   const uint32_t rem = (nbytes & 15u) >> 2;
   if (rem) {
-    if ((uint32_t)wave == ctr % (uint32_t)W && (uint32_t)lane < rem)
+    if ((uint32_t)wave == (ctr & wm) && (uint32_t)lane < rem)
       __builtin_amdgcn_global_load_lds(src + 16 * (size_t)n16 + 4 * lane, (lds_vptr)(lds + dst + 16 * n16), 4, 0, 0);
     ++ctr;
   }
@@ -685,7 +686,8 @@ __device__ __forceinline__ void dma_copy_strided(const char* src, size_t gstride
   const uint32_t upc = nb / ub;                       // units per chunk
   const uint32_t total = cnt * upc;
   const uint32_t ninst = (total + 63) >> 6;
-  for (uint32_t q = (uint32_t)((wave - (int)(ctr % (uint32_t)W) + W) % W); q < ninst; q += (uint32_t)W) {
+  const uint32_t wm = (uint32_t)W - 1;   // W is a power of two
+  for (uint32_t q = ((uint32_t)wave - ctr) & wm; q < ninst; q += (uint32_t)W) {
     const uint32_t u = q * 64 + (uint32_t)lane;
     if (u < total) {
       const uint32_t c = u / upc, o = u - c * upc;
@@ -811,7 +813,7 @@ __device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, u
 }
 
 template <class S, int OP, int U>
-__global__ __launch_bounds__(256) void k_tile(TileArgs a, int64_t nblocks, int remap) {
+__global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int remap) {
   extern __shared__ __align__(16) char lds[];
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
@@ -863,7 +865,7 @@ __global__ __launch_bounds__(256) void k_tile(TileArgs a, int64_t nblocks, int r
   // compute: node tn of the tile goes to wave tn mod W
   uint32_t t0 = 0;
   for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
-    for (int32_t n = (int32_t)((wave - (int)(t0 % (uint32_t)W) + W) % W); n < cnt; n += W) {
+    for (int32_t n = (int32_t)(((uint32_t)wave - t0) & (uint32_t)(W - 1)); n < cnt; n += W) {
       const uint32_t tn = t0 + (uint32_t)n;
       const uint32_t obase = (uint32_t)(first + n) * (uint32_t)a.L + (uint32_t)k0;
       uint32_t pos[kRec - 1], self;
@@ -1284,7 +1286,9 @@ hipError_t launch_op_t(int op, const Args& a, int U, int64_t nblocks, bool windo
 
 template <class S>
 hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int nitems, int64_t total,
-                            const Shape& sh, int num_cus, hipStream_t st) {
+                            const Shape& sh_in, int num_cus, hipStream_t st) {
+  Shape sh = sh_in;
+  if (sh.waves_per_block > 4) sh.waves_per_block = 4;
   int64_t grid = (int64_t)sh.blocks_per_cu * num_cus;
   if (grid > total) grid = total;
   if (grid < 1) grid = 1;
@@ -1303,6 +1307,13 @@ hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int n
 template <class S, int OP>
 hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds, int64_t nblocks, int remap,
                          hipStream_t st) {
+  if (lds > 65536) {
+    const void* fn = U == 1 ? reinterpret_cast<const void*>(&k_tile<S, OP, 1>)
+                     : U == 2 ? reinterpret_cast<const void*>(&k_tile<S, OP, 2>)
+                              : reinterpret_cast<const void*>(&k_tile<S, OP, 3>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   switch (U) {
     case 1: hipLaunchKernelGGL((k_tile<S, OP, 1>), g, b, lds, st, a, nblocks, remap); break;
     case 2: hipLaunchKernelGGL((k_tile<S, OP, 2>), g, b, lds, st, a, nblocks, remap); break;
@@ -1405,7 +1416,9 @@ int64_t blocks_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shap
 }
 
 hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V, int nlev,
-                     const void* in, void* out, const Shape& shape, hipStream_t stream) {
+                     const void* in, void* out, const Shape& shape_in, hipStream_t stream) {
+  Shape shape = shape_in;
+  if (shape.waves_per_block > 4) shape.waves_per_block = 4;   // 8 applies to LDS tiles only
   if (op == OP_LAP && t.lap_stride != kLapStride) return hipErrorInvalidValue;
   const Args a = make_args(op, t, ord, V, nlev, in, out, shape);
   const bool window = uses_window(op, nlev, shape);
@@ -1429,17 +1442,23 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   // Measured defaults at O1280 x 137 (rows: mode, KiB, tile rows, computing
   // and copying waves of the persistent form): scalar-input 1-ring operators,
   // vector-input ones, the two-ring Laplacian.
-  struct Def { int mode, kb, rows, cw, pw; };
+  // (mode, KiB, tile rows, computing waves, copying waves, lanes per node,
+  // waves per workgroup of the one-tile form)
+  struct Def { int mode, kb, rows, cw, pw, lanes, wpb; };
   const bool vec_in = op == OP_DIV || op == OP_GRADT;
   Def d;
-  if (dtype == DT_F32) d = op == OP_LAP ? Def{1, 64, 5, 12, 4} : vec_in ? Def{3, 64, 4, 0, 0} : Def{3, 32, 2, 0, 0};
-  else d = op == OP_LAP ? Def{3, 48, 4, 0, 0} : vec_in ? Def{2, 0, 0, 0, 0} : Def{1, 64, 3, 5, 3};
+  if (dtype == DT_F32)
+    d = op == OP_LAP ? Def{1, 64, 5, 12, 4, 32, 0} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 2, 0, 0, 0, 8};
+  else
+    d = op == OP_LAP ? Def{3, 48, 4, 0, 0, 0, 0} : vec_in ? Def{2, 0, 0, 0, 0, 0, 0} : Def{1, 64, 3, 6, 2, 0, 0};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;
   if (!e.band_rows) e.band_rows = d.rows;
   if (!e.tile_waves) e.tile_waves = d.cw;
   if (!e.producer_waves) e.producer_waves = d.pw;
+  if (!e.lanes_per_node) e.lanes_per_node = d.lanes;
+  if (d.wpb && e.waves_per_block == Shape().waves_per_block) e.waves_per_block = d.wpb;
   return e;
 }
 
@@ -1495,7 +1514,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& d
   const int64_t es = dtype == DT_F64 ? 8 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
   const int64_t row = op == OP_LAP ? kLapStride * (es + 2) : 8 * 2 * es + 16;
-  if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || dt.lds_bytes > 65536 ||
+  if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || dt.lds_bytes > kLdsPerCu ||
       dt.col_bytes != (int64_t)dt.KL * cin * es || dt.row_bytes != row)
     return hipErrorInvalidValue;
   TileArgs a;
@@ -1524,7 +1543,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& d
   // persistent double-buffered form
   const int nprod = shape.producer_waves > 0 ? shape.producer_waves : 2;
   const int ncons = shape.tile_waves > 0 ? shape.tile_waves : 6;
-  if (nprod + ncons > (dtype == DT_F64 ? 8 : 16)) return hipErrorInvalidValue;
+  if (nprod + ncons > (dtype == DT_F64 ? 8 : 16) || (nprod & (nprod - 1))) return hipErrorInvalidValue;
   const uint32_t buf_bytes = (dt.lds_bytes + (((uint32_t)dt.max_nodes * 4u + 15u) & ~15u) + 15u) & ~15u;
   // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
   int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;
@@ -1607,7 +1626,9 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
 }
 
 int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape) {
-  return blocks_for(op, ord, V, nlev, shape);
+  Shape sh = shape;
+  if (sh.waves_per_block > 4) sh.waves_per_block = 4;   // as launch_batched_t
+  return blocks_for(op, ord, V, nlev, sh);
 }
 
 hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V,
