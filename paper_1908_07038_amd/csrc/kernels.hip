@@ -1450,7 +1450,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   if (dtype == DT_F32)
     d = op == OP_LAP ? Def{1, 64, 5, 12, 4, 32, 0} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 2, 0, 0, 0, 8};
   else
-    d = op == OP_LAP ? Def{3, 48, 4, 0, 0, 0, 0} : vec_in ? Def{2, 0, 0, 0, 0, 0, 0} : Def{1, 64, 3, 6, 2, 0, 0};
+    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 160, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;
