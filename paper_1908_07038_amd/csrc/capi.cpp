@@ -74,6 +74,7 @@ struct atlas_mesh_s {
   std::map<std::pair<int, int>, NodeOrder> orders;   // (band rows, run) -> device node order
   OpTables host_nbr;                                   // neighbour tables only (tile building)
   std::map<std::vector<int64_t>, DevTiles> tilings;   // tiling key -> device tiles
+  std::map<std::vector<int64_t>, void*> records;      // tiling key + (op, dtype) -> packed node records
 
   ~atlas_mesh_s() {
     if (device >= 0) {
@@ -129,13 +130,11 @@ struct atlas_mesh_s {
     DevTiles dt;
     // eight pairs of padding: kernels fetch pairs eight at a time
     ht.segs.resize(ht.segs.size() + 16, 0);
-    ht.runs.resize(ht.runs.size() + 16, 0);
     dt.info = upload(ht.info);
     dt.segs = upload(ht.segs);
-    dt.runs = upload(ht.runs);
+    dt.order = upload(ht.order);
     dt.loc = upload(ht.loc);
     dt.ntiles = ht.ntiles;
-    dt.max_nodes = ht.max_nodes;
     dt.col_bytes = g.col_bytes;
     dt.row_bytes = g.row_bytes;
     int64_t lds = 0;
@@ -144,6 +143,30 @@ struct atlas_mesh_s {
     dt.lds_bytes = (uint32_t)lds;
     tilings[key] = dt;
     return dt;
+  }
+
+  // Node records of a tiling for (op, dtype), packed on the device on first
+  // use (one allocation of V records, kept until the mesh is freed).
+  const void* tile_records(const TileGeom& g, const Shape& sh, const DevTiles& dt, int op, int dtype,
+                           hipStream_t stream) {
+    const int h = sh.band_rows > 0 ? sh.band_rows : kDefaultTileRows;
+    const int sweep = sh.run_nodes > 0 ? sh.run_nodes : kDefaultTileSweep;
+    const std::vector<int64_t> key = {g.ring, h, sweep, g.col_bytes, g.row_bytes, g.budget, op, dtype};
+    std::lock_guard<std::mutex> lk(order_mu);
+    auto it = records.find(key);
+    if (it != records.end()) return it->second;
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)host.V * tile_record_bytes(op, dtype)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    allocations.push_back(p);
+    hipError_t e = pack_tile_records(op, dtype, tables(dtype), dt.order, dt.loc, host.V, p, stream);
+    // finished before any stream may read the records
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) throw std::runtime_error(std::string("packing tile records: ") + hipGetErrorString(e));
+    records[key] = p;
+    return p;
   }
 };
 
@@ -299,18 +322,19 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   const TileGeom tg = uses_tiles(op, dtype, nlev, sh) ? tile_geom(op, dtype, nlev, sh) : TileGeom();
   if (tg.KL > 0) {   // tiles asked for and a tile geometry fits the budget
     DevTiles dt;
+    const void* rec = nullptr;
     try {
       // tilings depend on the byte sizes only; the level chunk is the call's
       dt = mesh->tiles(tg, sh);
       dt.KL = tg.KL;
       dt.nchunks = tg.nchunks;
+      rec = mesh->tile_records(tg, sh, dt, op, dtype, (hipStream_t)stream);
     } catch (const std::bad_alloc&) {
       return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
     } catch (const std::exception& ex) {
       return fail(ATLAS_EHIP, ex.what());
     }
-    hipError_t e =
-        launch_tiles(op, dtype, mesh->tables(dtype), dt, nlev, in, out, sh, mesh->num_cus, (hipStream_t)stream);
+    hipError_t e = launch_tiles(op, dtype, dt, rec, nlev, in, out, sh, mesh->num_cus, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, kOpName[op]);
     return ATLAS_OK;
   }

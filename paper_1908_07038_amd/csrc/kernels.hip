@@ -607,26 +607,26 @@ __global__ __launch_bounds__(256) void k_batched(Args base, const BatchItem* __r
 
 // ---- LDS tiles -------------------------------------------------------------------
 //
-// A workgroup takes one tile: a set of nodes (runs of consecutive nodes from
-// the band order) and the sorted set of every column their stencils read,
+// A workgroup takes one tile: a set of nodes (a few latitude rows by one
+// longitude sector) and the sorted set of every column their stencils read,
 // stored as segments of consecutive nodes.  Columns of consecutive nodes are
-// contiguous in memory, so each segment is one contiguous block, which the
-// waves copy with direct global->LDS loads (64 dwords per instruction, no
-// registers involved) together with the tile's table rows (LDS positions and
-// coefficients); one wait and one barrier end the copy.  Each wave then takes
-// nodes of the tile in turn, 64 lanes = 64 levels, and reads its stencil and
-// tables from LDS; only the output goes back to memory.  No global load sits
-// on a node's critical path, every wave keeps many independent loads in
-// flight during the copy, and the workgroups sharing a CU overlap each
-// other's copy and compute phases.  Tiles follow the band order, so the halo
-// columns a tile shares with the tiles next to it are L2 hits.
+// contiguous in memory, so each segment is one contiguous block, which a wave
+// copies with direct global->LDS loads (16 bytes per lane, no registers
+// involved); the tile's node records (coefficients, LDS positions of the
+// stencil entries, node index), packed in tile order when the tiling is set
+// up, arrive in one more contiguous copy.  One wait and one barrier end the
+// copy.  Each wave then takes nodes of the tile in turn, 64 lanes = 64
+// levels, and reads its stencil and record from LDS; only the output goes
+// back to memory.  No global load sits on a node's critical path, every wave
+// keeps many independent loads in flight during the copy, and the
+// workgroups sharing a CU overlap each other's copy and compute phases.
+// Tiles stacked in latitude follow each other, so the halo columns they share
+// are L2 hits.
 
 struct TileArgs {
-  const int32_t* info;   // [ntiles + 1][4]: first segment, first run, columns, nodes
-  const int32_t* segs;   // [nseg][2]: first node, count
-  const int32_t* runs;   // [nrun][2]: first node, count
-  const uint16_t* loc;   // [V][stride] LDS positions; last entry: own position | count << 11
-  const void* coef;      // [V][stride] coefficient pairs (ring 1) or weights (ring 2)
+  const int32_t* info;   // [ntiles + 1][4]: first segment, first record, columns, nodes
+  const int32_t* segs;   // [nseg (+ 8 padding)][2]: first node, count
+  const char* rec;       // [V] node records in tile order (see tile_record_bytes)
   const void* in;
   void* out;
   int64_t ntiles;
@@ -634,6 +634,22 @@ struct TileArgs {
   int32_t KL;            // levels per chunk (L: whole columns)
   int32_t nchunks;
   int32_t nt;
+};
+
+// Node record of the tile path: coefficient row (8 pairs, ring 1; 24
+// weights, ring 2), LDS position row (8 or 24 uint16), node index (int32),
+// zero padding to 16 bytes.
+template <class S, int OP>
+struct TileRec {
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  static constexpr bool kRing2 = OP == OP_LAP;
+  static constexpr int kEntries = kRing2 ? kLapStride : 8;
+  static constexpr uint32_t kCoefB = kRing2 ? kEntries * sizeof(C) : 8 * sizeof(C2);
+  static constexpr uint32_t kLocB = 2 * kEntries;
+  static constexpr uint32_t kIdOff = kCoefB + kLocB;
+  static constexpr uint32_t kBytes = (kIdOff + 4 + 15) & ~15u;
+  static constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
 };
 
 constexpr int kLocCountShift = 11;
@@ -812,16 +828,43 @@ __device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, u
   }
 }
 
+// Copy of one tile (chunk) into an LDS buffer by W waves: the records as one
+// copy spread over the waves, then each column segment by one wave (segment
+// i by wave i mod W), so each wave sets up only its own copies.
+template <class S, int OP>
+__device__ __forceinline__ void tile_copy(const TileArgs& a, int64_t tile, int k0, int klc, char* buf, int wave,
+                                          int W, int lane) {
+  using R = TileRec<S, OP>;
+  const int32_t* inf = a.info + 4 * tile;
+  const int32_t seg0 = ld_uniform(inf), rec0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
+  const int32_t seg1 = ld_uniform(inf + 4);
+  const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
+  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
+  uint32_t ctr = 0;
+  dma_copy(a.rec + (size_t)rec0 * R::kBytes, buf, 0, (uint32_t)nnodes * R::kBytes, wave, W, lane, ctr);
+  const size_t gcol = (size_t)a.L * R::kCin * sizeof(S);                 // global column bytes
+  const char* in = static_cast<const char*>(a.in);
+  uint32_t p = 0, i = 0;
+  for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
+    if ((i & (uint32_t)(W - 1)) == (uint32_t)wave) {
+      uint32_t own = 0;
+      if (a.KL == a.L)
+        dma_copy(in + (size_t)first * gcol, buf, data_off + p * colB, (uint32_t)cnt * colB, 0, 1, lane, own);
+      else
+        dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * R::kCin * sizeof(S), gcol, (uint32_t)cnt, colB,
+                         buf, data_off + p * colB, 0, 1, lane, own);
+    }
+    p += (uint32_t)cnt;
+    ++i;
+  });
+}
+
 template <class S, int OP, int U>
 __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int remap) {
   extern __shared__ __align__(16) char lds[];
+  using R = TileRec<S, OP>;
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
-  constexpr bool kRing2 = OP == OP_LAP;
-  constexpr int kRec = kRing2 ? kLapStride : 8;
-  constexpr uint32_t kLocB = 2 * kRec;
-  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
-  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
   const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
   if (lb >= nblocks) return;
   const int64_t tile = lb / a.nchunks;
@@ -829,70 +872,62 @@ __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int r
   const int W = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int32_t* inf = a.info + 4 * tile;
-  const int32_t seg0 = ld_uniform(inf), run0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
-  const int32_t seg1 = ld_uniform(inf + 4), run1 = ld_uniform(inf + 5);
   const int k0 = chunk * a.KL;
   const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
-  const uint32_t colB = (uint32_t)klc * kCin * (uint32_t)sizeof(S);     // LDS column stride (this chunk)
-  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
-  const uint32_t data_off = loc_off + (uint32_t)nnodes * kLocB;
-  uint32_t ctr = 0;
-  // copy: table rows of the tile's nodes, then the stencil columns
-  {
-    uint32_t tn = 0;
-    for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
-      dma_copy(static_cast<const char*>(a.coef) + (size_t)first * kCoefB, lds, tn * kCoefB, (uint32_t)cnt * kCoefB,
-               wave, W, lane, ctr);
-      dma_copy(reinterpret_cast<const char*>(a.loc) + (size_t)first * kLocB, lds, loc_off + tn * kLocB,
-               (uint32_t)cnt * kLocB, wave, W, lane, ctr);
-      tn += (uint32_t)cnt;
-    });
-    const size_t gcol = (size_t)a.L * kCin * sizeof(S);                 // global column bytes
-    const char* in = static_cast<const char*>(a.in);
-    uint32_t p = 0;
-    for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
-      if (a.KL == a.L)
-        dma_copy(in + (size_t)first * gcol, lds, data_off + p * colB, (uint32_t)cnt * colB, wave, W, lane, ctr);
-      else
-        dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * kCin * sizeof(S), gcol, (uint32_t)cnt, colB, lds,
-                         data_off + p * colB, wave, W, lane, ctr);
-      p += (uint32_t)cnt;
-    });
-  }
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  tile_copy<S, OP>(a, tile, k0, klc, lds, wave, W, lane);
+  const int32_t nnodes = ld_uniform(a.info + 4 * tile + 3);
+  const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);
+  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
+  __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
   __syncthreads();
   // compute: node tn of the tile goes to wave tn mod W
-  uint32_t t0 = 0;
-  for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
-    for (int32_t n = (int32_t)(((uint32_t)wave - t0) & (uint32_t)(W - 1)); n < cnt; n += W) {
-      const uint32_t tn = t0 + (uint32_t)n;
-      const uint32_t obase = (uint32_t)(first + n) * (uint32_t)a.L + (uint32_t)k0;
-      uint32_t pos[kRec - 1], self;
-      int ne;
-      tile_positions<kRec>(lds, loc_off + tn * kLocB, pos, self, ne);
-      if constexpr (kRing2) {
-        C w[kRec - 1];
+  for (int32_t tn = wave; tn < nnodes; tn += W) {
+    const uint32_t ro = (uint32_t)tn * R::kBytes;
+    const uint32_t obase = uni((uint32_t)lds_ld<int32_t>(lds, ro + R::kIdOff)) * (uint32_t)a.L + (uint32_t)k0;
+    uint32_t pos[R::kEntries - 1], self;
+    int ne;
+    tile_positions<R::kEntries>(lds, ro + R::kCoefB, pos, self, ne);
+    if constexpr (R::kRing2) {
+      C w[R::kEntries - 1];
 #pragma unroll
-        for (int s = 0; s < kRec - 1; ++s) w[s] = lds_ld<C>(lds, tn * kCoefB + s * (uint32_t)sizeof(C));
-        if (ne <= 18) tile_node2<S, U, 18>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
-        else tile_node2<S, 1, kRec - 1>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
-      } else {
-        C2 cf[7];
+      for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C));
+      if (ne <= 18) tile_node2<S, U, 18>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
+      else tile_node2<S, 1, R::kEntries - 1>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
+    } else {
+      C2 cf[7];
 #pragma unroll
-        for (int s = 0; s < 7; ++s) cf[s] = lds_ld<C2>(lds, tn * kCoefB + s * (uint32_t)sizeof(C2));
-        const C2 dg = lds_ld<C2>(lds, tn * kCoefB + 7 * (uint32_t)sizeof(C2));
-        switch (ne) {
-          case 6: tile_node1<S, OP, U, 6>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-          case 5: tile_node1<S, OP, 1, 5>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-          case 7: tile_node1<S, OP, 1, 7>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-          case 4: tile_node1<S, OP, 1, 4>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-          default: tile_node1<S, OP, 1, 3>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-        }
+      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
+      const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
+      switch (ne) {
+        case 6: tile_node1<S, OP, U, 6>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        case 5: tile_node1<S, OP, 1, 5>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        case 7: tile_node1<S, OP, 1, 7>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        case 4: tile_node1<S, OP, 1, 4>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        default: tile_node1<S, OP, 1, 3>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
       }
     }
-    t0 += (uint32_t)cnt;
-  });
+  }
+}
+
+// Packs the node records of a tiling in tile order: record q is node
+// order[q]; one thread per dword of the records.
+template <class S, int OP>
+__global__ __launch_bounds__(256) void k_pack_records(const int32_t* __restrict__ order,
+                                                      const void* __restrict__ coef,
+                                                      const uint16_t* __restrict__ loc, int64_t V,
+                                                      uint32_t* __restrict__ rec) {
+  using R = TileRec<S, OP>;
+  constexpr uint32_t kDw = R::kBytes / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V * kDw) return;
+  const int64_t q = t / kDw;
+  const uint32_t d = (uint32_t)(t - q * kDw);
+  const int64_t i = order[q];
+  uint32_t v = 0;
+  if (d < R::kCoefB / 4) v = static_cast<const uint32_t*>(coef)[i * (R::kCoefB / 4) + d];
+  else if (d < R::kIdOff / 4) v = reinterpret_cast<const uint32_t*>(loc)[i * (R::kLocB / 4) + (d - R::kCoefB / 4)];
+  else if (d == R::kIdOff / 4) v = (uint32_t)i;
+  rec[t] = v;
 }
 
 // ---- persistent LDS tiles, double buffered ------------------------------------
@@ -902,45 +937,8 @@ __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int r
 // their own wait) while consumer waves evaluate tile n from the other; one
 // barrier per tile swaps the buffers.  Consumers use the lane mapping of the
 // gather path: P lanes per node, 64 / P nodes per wave step, lane t handling
-// levels t, t + P, ...; each lane reads its node's LDS positions and
-// coefficients from the tile's table rows in LDS (broadcast reads).  The
-// producers also store the tile's node indices into LDS.
-
-__device__ __forceinline__ void tile_issue(const TileArgs& a, int64_t lb, char* buf, uint32_t kCoefB, uint32_t kLocB,
-                                           int kCin, uint32_t es, int pw, int NP, int lane) {
-  const int64_t tile = lb / a.nchunks;
-  const int chunk = (int)(lb - tile * a.nchunks);
-  const int32_t* inf = a.info + 4 * tile;
-  const int32_t seg0 = ld_uniform(inf), run0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
-  const int32_t seg1 = ld_uniform(inf + 4), run1 = ld_uniform(inf + 5);
-  const int k0 = chunk * a.KL;
-  const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
-  const uint32_t colB = (uint32_t)klc * kCin * es;   // LDS column stride (this chunk)
-  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
-  const uint32_t ids_off = loc_off + (uint32_t)nnodes * kLocB;
-  const uint32_t data_off = ids_off + (((uint32_t)nnodes * 4u + 15u) & ~15u);
-  uint32_t ctr = 0, tn = 0;
-  for_pairs(a.runs, run0, run1, [&](int32_t first, int32_t cnt) {
-    dma_copy(static_cast<const char*>(a.coef) + (size_t)first * kCoefB, buf, tn * kCoefB, (uint32_t)cnt * kCoefB, pw,
-             NP, lane, ctr);
-    dma_copy(reinterpret_cast<const char*>(a.loc) + (size_t)first * kLocB, buf, loc_off + tn * kLocB,
-             (uint32_t)cnt * kLocB, pw, NP, lane, ctr);
-    for (int32_t n = pw * 64 + lane; n < cnt; n += NP * 64)
-      *reinterpret_cast<int32_t*>(buf + ids_off + 4 * (tn + (uint32_t)n)) = first + n;
-    tn += (uint32_t)cnt;
-  });
-  const size_t gcol = (size_t)a.L * kCin * es;
-  const char* in = static_cast<const char*>(a.in);
-  uint32_t p = 0;
-  for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
-    if (a.KL == a.L)
-      dma_copy(in + (size_t)first * gcol, buf, data_off + p * colB, (uint32_t)cnt * colB, pw, NP, lane, ctr);
-    else
-      dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * kCin * es, gcol, (uint32_t)cnt, colB, buf,
-                       data_off + p * colB, pw, NP, lane, ctr);
-    p += (uint32_t)cnt;
-  });
-}
+// levels t, t + P, ...; each lane reads its node's record from LDS (broadcast
+// reads).
 
 // P-lane evaluation of 1-ring nodes from an LDS tile: NS slots (7 = padded
 // with the node itself and zero coefficients).
@@ -1007,56 +1005,51 @@ __device__ __forceinline__ void tile_lanes2(const TileArgs& a, const char* buf, 
 template <class S, int OP, int U>
 __device__ __forceinline__ void tile_consume(const TileArgs& a, int64_t lb, const char* buf, int cw, int NC, int P,
                                              int lane) {
+  using R = TileRec<S, OP>;
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
-  constexpr bool kRing2 = OP == OP_LAP;
-  constexpr int kRec = kRing2 ? kLapStride : 8;
-  constexpr uint32_t kLocB = 2 * kRec;
-  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
-  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
   const int64_t tile = lb / a.nchunks;
   const int chunk = (int)(lb - tile * a.nchunks);
   const int32_t nnodes = ld_uniform(a.info + 4 * tile + 3);
   const int k0 = chunk * a.KL;
   const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
-  const uint32_t colB = (uint32_t)klc * kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
-  const uint32_t loc_off = (uint32_t)nnodes * kCoefB;
-  const uint32_t ids_off = loc_off + (uint32_t)nnodes * kLocB;
-  const uint32_t data_off = ids_off + (((uint32_t)nnodes * 4u + 15u) & ~15u);
+  const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
+  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
   const int G = 64 / P;
   const int j = lane / P, t = lane - (lane / P) * P;
   for (int32_t tn0 = cw * G; tn0 < nnodes; tn0 += NC * G) {
     const int32_t tn = tn0 + j;
     const bool ok = j < G && tn < nnodes;
-    const uint32_t tq = (uint32_t)(ok ? tn : tn0);
-    const int32_t i = lds_ld<int32_t>(buf, ids_off + 4 * tq);
+    const uint32_t ro = (uint32_t)(ok ? tn : tn0) * R::kBytes;
+    const int32_t i = lds_ld<int32_t>(buf, ro + R::kIdOff);
     const uint32_t obase = (uint32_t)i * (uint32_t)a.L + (uint32_t)k0;
-    uint32_t w32[kRec / 2];
+    uint32_t w32[R::kEntries / 2];
 #pragma unroll
-    for (int q = 0; q < kRec / 8; ++q) {
-      const uint4 r = lds_ld<uint4>(buf, loc_off + tq * kLocB + 16 * q);
+    for (int q = 0; q < R::kEntries / 8; ++q) {
+      const uint4 r = lds_ld<uint4>(buf, ro + R::kCoefB + 16 * q);
       w32[4 * q] = r.x;
       w32[4 * q + 1] = r.y;
       w32[4 * q + 2] = r.z;
       w32[4 * q + 3] = r.w;
     }
-    uint32_t so[kRec - 1];
+    uint32_t so[R::kEntries - 1];
 #pragma unroll
-    for (int s = 0; s < kRec - 1; ++s) so[s] = data_off + ((s & 1) ? (w32[s >> 1] >> 16) : (w32[s >> 1] & 0xffffu)) * colB;
-    const uint32_t last = w32[kRec / 2 - 1] >> 16;
+    for (int q = 0; q < R::kEntries - 1; ++q)
+      so[q] = data_off + ((q & 1) ? (w32[q >> 1] >> 16) : (w32[q >> 1] & 0xffffu)) * colB;
+    const uint32_t last = w32[R::kEntries / 2 - 1] >> 16;
     const uint32_t xo = data_off + (last & ((1u << kLocCountShift) - 1)) * colB;
     const int ne = (int)(last >> kLocCountShift);
-    if constexpr (kRing2) {
-      C w[kRec - 1];
+    if constexpr (R::kRing2) {
+      C w[R::kEntries - 1];
 #pragma unroll
-      for (int s = 0; s < kRec - 1; ++s) w[s] = lds_ld<C>(buf, tq * kCoefB + s * (uint32_t)sizeof(C));
+      for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(buf, ro + q * (uint32_t)sizeof(C));
       if (__all(ne <= 18)) tile_lanes2<S, 18, U>(a, buf, so, xo, w, obase, ok, t, P, klc);
-      else tile_lanes2<S, kRec - 1, 1>(a, buf, so, xo, w, obase, ok, t, P, klc);
+      else tile_lanes2<S, R::kEntries - 1, 1>(a, buf, so, xo, w, obase, ok, t, P, klc);
     } else {
       C2 cf[7];
 #pragma unroll
-      for (int s = 0; s < 7; ++s) cf[s] = lds_ld<C2>(buf, tq * kCoefB + s * (uint32_t)sizeof(C2));
-      const C2 dg = lds_ld<C2>(buf, tq * kCoefB + 7 * (uint32_t)sizeof(C2));
+      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(buf, ro + q * (uint32_t)sizeof(C2));
+      const C2 dg = lds_ld<C2>(buf, ro + 7 * (uint32_t)sizeof(C2));
       if (__all(ne == 6)) tile_lanes1<S, OP, 6, U>(a, buf, data_off, colB, so, xo, cf, dg, obase, ok, t, P, klc);
       else tile_lanes1<S, OP, 7, 1>(a, buf, data_off, colB, so, xo, cf, dg, obase, ok, t, P, klc);
     }
@@ -1068,17 +1061,20 @@ __device__ __forceinline__ void tile_consume(const TileArgs& a, int64_t lb, cons
 template <class S>
 constexpr int kTile2Threads = sizeof(S) == 8 ? 512 : 1024;
 
+// Copy of logical block lb (tile, level chunk) by the NP producer waves.
+template <class S, int OP>
+__device__ __forceinline__ void tile_issue(const TileArgs& a, int64_t lb, char* buf, int pw, int NP, int lane) {
+  const int64_t tile = lb / a.nchunks;
+  const int chunk = (int)(lb - tile * a.nchunks);
+  const int k0 = chunk * a.KL;
+  const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
+  tile_copy<S, OP>(a, tile, k0, klc, buf, pw, NP, lane);
+}
+
 template <class S, int OP, int U>
 __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t nblocks, int remap, uint32_t buf_bytes, int nprod,
                                                int P) {
   extern __shared__ __align__(16) char lds[];
-  using C = typename Traits<S>::C;
-  using C2 = typename Traits<S>::C2;
-  constexpr bool kRing2 = OP == OP_LAP;
-  constexpr int kRec = kRing2 ? kLapStride : 8;
-  constexpr uint32_t kLocB = 2 * kRec;
-  constexpr uint32_t kCoefB = kRing2 ? kRec * sizeof(C) : 8 * sizeof(C2);
-  constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
   const int W = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1099,7 +1095,7 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
   const bool producer = wave < nprod;
   uint32_t cur = 0;
   if (producer && lb < end) {
-    tile_issue(a, lb, lds, kCoefB, kLocB, kCin, (uint32_t)sizeof(S), wave, nprod, lane);
+    tile_issue<S, OP>(a, lb, lds, wave, nprod, lane);
     __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
   }
   __syncthreads();
@@ -1107,7 +1103,7 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
     const int64_t nx = lb + step;
     if (producer) {
       if (nx < end) {
-        tile_issue(a, nx, lds + (cur ^ buf_bytes), kCoefB, kLocB, kCin, (uint32_t)sizeof(S), wave, nprod, lane);
+        tile_issue<S, OP>(a, nx, lds + (cur ^ buf_bytes), wave, nprod, lane);
         __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
       }
     } else {
@@ -1448,7 +1444,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   const bool vec_in = op == OP_DIV || op == OP_GRADT;
   Def d;
   if (dtype == DT_F32)
-    d = op == OP_LAP ? Def{1, 64, 5, 12, 4, 32, 0} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 2, 0, 0, 0, 8};
+    d = op == OP_LAP ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else
     d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 160, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
@@ -1472,7 +1468,7 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   const int64_t es = dtype == DT_F64 ? 8 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
   g.ring = op == OP_LAP ? 2 : 1;
-  g.row_bytes = g.ring == 2 ? kLapStride * (es + 2) : 8 * 2 * es + 16;
+  g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
   // Column chunk: whole columns if a tile of `want` columns (and half as many
   // nodes' table rows) fits, else the largest equal chunks that do; if even
@@ -1508,21 +1504,44 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   return g;
 }
 
-hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
+int64_t tile_record_bytes(int op, int dtype) {
+  switch (op * 2 + (dtype == DT_F64 ? 1 : 0)) {
+    case OP_LAP * 2: return TileRec<float, OP_LAP>::kBytes;
+    case OP_LAP * 2 + 1: return TileRec<double, OP_LAP>::kBytes;
+    default: return dtype == DT_F64 ? TileRec<double, OP_GRAD>::kBytes : TileRec<float, OP_GRAD>::kBytes;
+  }
+}
+
+hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,
+                             int64_t V, void* rec, hipStream_t stream) {
+  const int64_t n = V * (tile_record_bytes(op, dtype) / 4);
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  const void* coef = op == OP_LAP ? t.lap_w : t.coef[op];
+  uint32_t* r = static_cast<uint32_t*>(rec);
+  const bool f64 = dtype == DT_F64;
+  if (op == OP_LAP) {
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_LAP>), g, b, 0, stream, order, coef, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_LAP>), g, b, 0, stream, order, coef, loc, V, r);
+  } else {
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRAD>), g, b, 0, stream, order, coef, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_GRAD>), g, b, 0, stream, order, coef, loc, V, r);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
                         void* out, const Shape& shape, int num_cus, hipStream_t stream) {
   // the tiling's LDS footprint must be the one the kernel lays out
   const int64_t es = dtype == DT_F64 ? 8 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
-  const int64_t row = op == OP_LAP ? kLapStride * (es + 2) : 8 * 2 * es + 16;
+  const int64_t row = tile_record_bytes(op, dtype);
   if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || dt.lds_bytes > kLdsPerCu ||
       dt.col_bytes != (int64_t)dt.KL * cin * es || dt.row_bytes != row)
     return hipErrorInvalidValue;
   TileArgs a;
   a.info = dt.info;
   a.segs = dt.segs;
-  a.runs = dt.runs;
-  a.loc = dt.loc;
-  a.coef = op == OP_LAP ? t.lap_w : t.coef[op];
+  a.rec = static_cast<const char*>(rec);
   a.in = in;
   a.out = out;
   a.ntiles = dt.ntiles;
@@ -1544,7 +1563,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& d
   const int nprod = shape.producer_waves > 0 ? shape.producer_waves : 2;
   const int ncons = shape.tile_waves > 0 ? shape.tile_waves : 6;
   if (nprod + ncons > (dtype == DT_F64 ? 8 : 16) || (nprod & (nprod - 1))) return hipErrorInvalidValue;
-  const uint32_t buf_bytes = (dt.lds_bytes + (((uint32_t)dt.max_nodes * 4u + 15u) & ~15u) + 15u) & ~15u;
+  const uint32_t buf_bytes = (dt.lds_bytes + 15u) & ~15u;
   // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
   int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;
   while (per_cu > 1 && (uint64_t)2 * buf_bytes * per_cu > kLdsPerCu) --per_cu;

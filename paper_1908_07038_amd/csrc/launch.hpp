@@ -74,12 +74,11 @@ int window_slices(int nlev, const Shape& sh);
 struct DevTiles {
   const int32_t* info = nullptr;
   const int32_t* segs = nullptr;
-  const int32_t* runs = nullptr;
-  const uint16_t* loc = nullptr;
+  const int32_t* order = nullptr;   // [V] nodes in tile order
+  const uint16_t* loc = nullptr;    // [V][8 or 24] LDS positions (source of the records)
   int64_t ntiles = 0;
   int KL = 0, nchunks = 1;  // level chunk of the launch (set per call)
   uint32_t lds_bytes = 0;   // largest tile footprint
-  int32_t max_nodes = 0;    // most nodes in a tile
   int64_t col_bytes = 0, row_bytes = 0;   // LDS bytes per column chunk / node the tiling was cut for
 };
 // Geometry of a tiled launch: stencil ring, level chunking (KL levels per
@@ -96,7 +95,13 @@ bool uses_tiles(int op, int dtype, int nlev, const Shape& sh);
 // resolved shape runs, e.g. "k_tile<float, 0, 3>".
 void kernel_label(int op, int dtype, int nlev, const Shape& resolved, char* buf, int len);
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh);
-hipError_t launch_tiles(int op, int dtype, const DevTables& t, const DevTiles& dt, int nlev, const void* in,
+// Bytes of one node record of the tile path (LDS bytes per tile node).
+int64_t tile_record_bytes(int op, int dtype);
+// Packs a tiling's node records for (op, dtype) into rec ([V] records in tile
+// order: coefficients, LDS positions, node index).
+hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,
+                             int64_t V, void* rec, hipStream_t stream);
+hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
                         void* out, const Shape& shape, int num_cus, hipStream_t stream);
 
 // Single-field operator launch; in/out are device pointers of the dtype and

@@ -106,9 +106,11 @@ struct HaloTiles {
   int ring = 1;
   int stride = 8;                  // loc entries per node: 8 (ring 1) or kLapStride (ring 2)
   int64_t ntiles = 0;
-  std::vector<int32_t> info;       // [ntiles + 1][4]: first segment, first run, columns, nodes
+  std::vector<int32_t> info;       // [ntiles + 1][4]: first segment, first position in order, columns, nodes
   std::vector<int32_t> segs;       // [nseg][2]: first node, count
-  std::vector<int32_t> runs;       // [nrun][2]: first node, count (the tile's own nodes)
+  std::vector<int32_t> order;      // [V]: the nodes, tile by tile
+  std::vector<int32_t> runs;       // [nrun][2]: first node, count (the tiles' nodes as runs)
+  std::vector<int32_t> run_off;    // [ntiles + 1]: first run of each tile
   std::vector<uint16_t> loc;       // [V][stride]
   int max_cols = 0, max_nodes = 0; // largest tile
 };

@@ -643,11 +643,13 @@ void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_r
   auto close_tile = [&]() {
     if (nodes.empty()) return;
     std::sort(cols.begin(), cols.end());
-    const int32_t seg0 = (int32_t)(out.segs.size() / 2), run0 = (int32_t)(out.runs.size() / 2);
+    const int32_t seg0 = (int32_t)(out.segs.size() / 2);
     out.info.push_back(seg0);
-    out.info.push_back(run0);
+    out.info.push_back((int32_t)out.order.size());
     out.info.push_back((int32_t)cols.size());
     out.info.push_back((int32_t)nodes.size());
+    out.run_off.push_back((int32_t)(out.runs.size() / 2));
+    out.order.insert(out.order.end(), nodes.begin(), nodes.end());
     for (size_t c = 0; c < cols.size(); ++c) {
       if (c > 0 && cols[c] == cols[c - 1] + 1) {
         ++out.segs.back();
@@ -713,9 +715,10 @@ void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_r
   out.ntiles = tile;
   // sentinel: one past the last tile
   out.info.push_back((int32_t)(out.segs.size() / 2));
-  out.info.push_back((int32_t)(out.runs.size() / 2));
+  out.info.push_back((int32_t)out.order.size());
   out.info.push_back(0);
   out.info.push_back(0);
+  out.run_off.push_back((int32_t)(out.runs.size() / 2));
 }
 
 }  // namespace atlasnabla

@@ -1,6 +1,7 @@
 // Host check of the LDS tile builder (build_halo_tiles): for a mesh and a
 // tile geometry given on the command line it verifies that
-//   - every node belongs to exactly one tile,
+//   - every node belongs to exactly one tile, listed in the tile-by-tile
+//     node order at the tile's position,
 //   - each tile's segments are in-range, sorted, disjoint runs of columns,
 //   - each tile's footprint columns * col_bytes + nodes * row_bytes fits the
 //     budget, and the column count fits the position field,
@@ -48,6 +49,8 @@ int main(int argc, char** argv) {
     ++bad;
   };
   if ((int64_t)ht.info.size() != 4 * (ht.ntiles + 1)) err("info size", (int64_t)ht.info.size(), ht.ntiles);
+  if ((int64_t)ht.order.size() != m.V) err("order size", (int64_t)ht.order.size(), m.V);
+  if ((int64_t)ht.run_off.size() != ht.ntiles + 1) err("run_off size", (int64_t)ht.run_off.size(), ht.ntiles);
   std::vector<int> seen(m.V, 0);
   std::mt19937_64 rng(7);
   std::normal_distribution<double> nd;
@@ -58,7 +61,9 @@ int main(int argc, char** argv) {
   double cols_total = 0;
   for (int64_t tl = 0; tl < ht.ntiles && bad < 10; ++tl) {
     const int32_t* in = &ht.info[4 * tl];
-    const int seg0 = in[0], run0 = in[1], ncols = in[2], nnodes = in[3], seg1 = in[4], run1 = in[5];
+    const int seg0 = in[0], pos0 = in[1], ncols = in[2], nnodes = in[3], seg1 = in[4], pos1 = in[5];
+    const int run0 = ht.run_off[tl], run1 = ht.run_off[tl + 1];
+    if (pos1 - pos0 != nnodes) err("order span", tl, pos1 - pos0);
     if (ncols * col_bytes + nnodes * row_bytes > budget) err("over budget", tl, ncols);
     if (ncols > kMaxTileCols) err("too many columns", tl, ncols);
     std::vector<int32_t> col;
@@ -79,6 +84,7 @@ int main(int argc, char** argv) {
           continue;
         }
         ++seen[i];
+        if (pos0 + nn >= (int)ht.order.size() || ht.order[pos0 + nn] != i) err("order entry", tl, nn);
         ++nn;
         const uint16_t* l = &ht.loc[(size_t)stride * i];
         const int self = l[stride - 1] & kMaxTileCols, cnt = l[stride - 1] >> kLocCountShift;

@@ -119,7 +119,7 @@ def test_describe_resolves_the_default_paths():
     cases = [(pa.OP_GRADIENT, pa.F32, 137, "k_tile<float, 0, 3>"),
              (pa.OP_DIVERGENCE_ADJOINT, pa.F32, 137, "k_tile<float, 3, 3>"),
              (pa.OP_DIVERGENCE, pa.F32, 137, "k_tile<float, 1, 3>"),
-             (pa.OP_LAPLACIAN, pa.F32, 137, "k_tile2<float, 4, 3>"),
+             (pa.OP_LAPLACIAN, pa.F32, 137, "k_tile<float, 4, 3>"),
              (pa.OP_GRADIENT, pa.F64, 137, "k_tile<double, 0, 3>"),
              (pa.OP_DIVERGENCE, pa.F64, 137, "k_tile<double, 1, 3>"),
              (pa.OP_LAPLACIAN, pa.F64, 137, "k_tile<double, 4, 3>"),
