@@ -319,7 +319,10 @@ int run_op(atlas_mesh_t mesh, int op, int dtype, int32_t nlev, const void* in, v
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
   Shape sh = resolve_shape(op, dtype, nlev, shape_override ? *shape_override : mesh->shape[op][dtype]);
-  const TileGeom tg = uses_tiles(op, dtype, nlev, sh) ? tile_geom(op, dtype, nlev, sh) : TileGeom();
+  TileGeom tg = uses_tiles(op, dtype, nlev, sh) ? tile_geom(op, dtype, nlev, sh) : TileGeom();
+  // BF16 tiles copy whole dwords around each column segment: they need a
+  // 4-byte aligned field (else the row-window walk or gather runs)
+  if (dtype == ATLAS_BF16 && ((uintptr_t)in & 3u)) tg.KL = 0;
   if (tg.KL > 0) {   // tiles asked for and a tile geometry fits the budget
     DevTiles dt;
     const void* rec = nullptr;

@@ -663,6 +663,7 @@ typedef __attribute__((address_space(3))) void* lds_vptr;
 constexpr int kWaitLgkm0 = 0xC07F;
 
 constexpr uint64_t kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
+constexpr int64_t kBf16ColExtra = 12;        // BF16 tiles: LDS bytes per column beyond the data
 
 // Direct loads of nbytes (a multiple of 4) from global src to LDS byte offset
 // dst: 16 bytes per lane (lane l of instruction q moves bytes 16 (64 q + l)
@@ -740,6 +741,20 @@ __device__ __forceinline__ T lds_ld(const char* lds, uint32_t off) {
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
+// One stencil value from an LDS tile, in the arithmetic type X (BF16 columns
+// widen to FP32).
+template <class S, class X>
+__device__ __forceinline__ X lds_elem(const char* lds, uint32_t off) {
+  if constexpr (sizeof(S) != 2) {
+    return lds_ld<X>(lds, off);
+  } else if constexpr (sizeof(X) == 4) {
+    return bf16_to_f32(lds_ld<uint16_t>(lds, off));
+  } else {
+    const uint32_t w = lds_ld<uint32_t>(lds, off);
+    return make_float2(bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16));
+  }
+}
+
 // LDS positions of a node's entries (wave-uniform): pos[s] for the stencil
 // slots, own position and entry count from the last record entry.
 template <int NREC>
@@ -763,14 +778,11 @@ __device__ __forceinline__ void tile_positions(const char* lds, uint32_t off, ui
 
 // One node of a 1-ring operator: DEG slots, U slices of 64 levels per step.
 template <class S, int OP, int U, int DEG>
-__device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, uint32_t data_off, uint32_t colB,
-                                           const uint32_t* pos, uint32_t self, const typename Traits<S>::C2* cf,
-                                           typename Traits<S>::C2 dg, uint32_t obase, int klc, int lane) {
+__device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
+                                           const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
+                                           uint32_t obase, int klc, int lane) {
   using X = typename WinT<S, OP>::X;
-  uint32_t so[DEG];
-#pragma unroll
-  for (int s = 0; s < DEG; ++s) so[s] = data_off + pos[s] * colB;
-  const uint32_t xo = data_off + self * colB;
+  constexpr uint32_t kEl = (uint32_t)sizeof(S) * TileRec<S, OP>::kCin;   // bytes per level in LDS
   S* __restrict__ out = static_cast<S*>(a.out);
   for (int kb = 0; kb < klc; kb += 64 * U) {
     X v[U][DEG], x0[U];
@@ -779,10 +791,10 @@ __device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, u
     for (int u = 0; u < U; ++u) {
       const int k = kb + 64 * u + lane;
       st[u] = k < klc;
-      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(X);
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * kEl;
 #pragma unroll
-      for (int s = 0; s < DEG; ++s) v[u][s] = lds_ld<X>(lds, so[s] + kk);
-      x0[u] = lds_ld<X>(lds, xo + kk);
+      for (int s = 0; s < DEG; ++s) v[u][s] = lds_elem<S, X>(lds, so[s] + kk);
+      x0[u] = lds_elem<S, X>(lds, xo + kk);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -793,14 +805,9 @@ __device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, u
 // One node of the two-ring Laplacian: NS entries (padded with the node itself
 // and zero weights, which add exact zeros), sum_m W_im (f_m - f_i).
 template <class S, int U, int NS>
-__device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, uint32_t data_off, uint32_t colB,
-                                           const uint32_t* pos, uint32_t self, const typename Traits<S>::C* w,
-                                           uint32_t obase, int klc, int lane) {
+__device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
+                                           const typename Traits<S>::C* w, uint32_t obase, int klc, int lane) {
   using C = typename Traits<S>::C;
-  uint32_t so[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) so[s] = data_off + pos[s] * colB;
-  const uint32_t xo = data_off + self * colB;
   S* __restrict__ out = static_cast<S*>(a.out);
   for (int kb = 0; kb < klc; kb += 64 * U) {
     C v[U][NS], x0[U];
@@ -809,10 +816,10 @@ __device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, u
     for (int u = 0; u < U; ++u) {
       const int k = kb + 64 * u + lane;
       st[u] = k < klc;
-      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(C);
+      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(S);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) v[u][s] = lds_ld<C>(lds, so[s] + kk);
-      x0[u] = lds_ld<C>(lds, xo + kk);
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_elem<S, C>(lds, so[s] + kk);
+      x0[u] = lds_elem<S, C>(lds, xo + kk);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -836,27 +843,66 @@ __device__ __forceinline__ void tile_copy(const TileArgs& a, int64_t tile, int k
                                           int W, int lane) {
   using R = TileRec<S, OP>;
   const int32_t* inf = a.info + 4 * tile;
-  const int32_t seg0 = ld_uniform(inf), rec0 = ld_uniform(inf + 1), nnodes = ld_uniform(inf + 3);
+  const int32_t seg0 = ld_uniform(inf), rec0 = ld_uniform(inf + 1), ncols = ld_uniform(inf + 2),
+                nnodes = ld_uniform(inf + 3);
   const int32_t seg1 = ld_uniform(inf + 4);
   const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
-  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
   uint32_t ctr = 0;
   dma_copy(a.rec + (size_t)rec0 * R::kBytes, buf, 0, (uint32_t)nnodes * R::kBytes, wave, W, lane, ctr);
   const size_t gcol = (size_t)a.L * R::kCin * sizeof(S);                 // global column bytes
   const char* in = static_cast<const char*>(a.in);
   uint32_t p = 0, i = 0;
-  for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
-    if ((i & (uint32_t)(W - 1)) == (uint32_t)wave) {
-      uint32_t own = 0;
-      if (a.KL == a.L)
-        dma_copy(in + (size_t)first * gcol, buf, data_off + p * colB, (uint32_t)cnt * colB, 0, 1, lane, own);
-      else
-        dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * R::kCin * sizeof(S), gcol, (uint32_t)cnt, colB,
-                         buf, data_off + p * colB, 0, 1, lane, own);
-    }
-    p += (uint32_t)cnt;
-    ++i;
-  });
+  if constexpr (sizeof(S) == 2) {
+    // BF16 columns may start 2 bytes into a dword: each segment is copied as
+    // the dword-aligned span around it, placed so that LDS and memory agree
+    // mod 4, and its columns' LDS offsets go to a table after the records.
+    const uint32_t tab = (uint32_t)nnodes * R::kBytes;
+    uint32_t cur = tab + (((uint32_t)ncols * 4u + 15u) & ~15u);
+    for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
+      const size_t g0 = (size_t)first * gcol;
+      const uint32_t mis = (uint32_t)(g0 & 3u);
+      const uint32_t nb = (uint32_t)((((g0 + (size_t)cnt * colB) + 3u) & ~(size_t)3u) - (g0 - mis));
+      if ((i & (uint32_t)(W - 1)) == (uint32_t)wave) {
+        uint32_t own = 0;
+        dma_copy(in + (g0 - mis), buf, cur, nb, 0, 1, lane, own);
+        for (int32_t c = lane; c < cnt; c += 64)
+          *reinterpret_cast<uint32_t*>(buf + tab + 4 * (p + (uint32_t)c)) = cur + mis + (uint32_t)c * colB;
+      }
+      cur += nb;
+      p += (uint32_t)cnt;
+      ++i;
+    });
+  } else {
+    const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
+    for_pairs(a.segs, seg0, seg1, [&](int32_t first, int32_t cnt) {
+      if ((i & (uint32_t)(W - 1)) == (uint32_t)wave) {
+        uint32_t own = 0;
+        if (a.KL == a.L)
+          dma_copy(in + (size_t)first * gcol, buf, data_off + p * colB, (uint32_t)cnt * colB, 0, 1, lane, own);
+        else
+          dma_copy_strided(in + (size_t)first * gcol + (size_t)k0 * R::kCin * sizeof(S), gcol, (uint32_t)cnt, colB,
+                           buf, data_off + p * colB, 0, 1, lane, own);
+      }
+      p += (uint32_t)cnt;
+      ++i;
+    });
+  }
+}
+
+// LDS offsets of a node's stencil columns from their tile positions: a
+// fixed stride for FP32/FP64, the offset table for BF16.
+template <class S, int N>
+__device__ __forceinline__ void tile_offsets(const char* lds, uint32_t tab, uint32_t data_off, uint32_t colB,
+                                             const uint32_t* pos, uint32_t self, uint32_t* so, uint32_t& xo) {
+  if constexpr (sizeof(S) == 2) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) so[q] = uni(lds_ld<uint32_t>(lds, tab + 4 * pos[q]));
+    xo = uni(lds_ld<uint32_t>(lds, tab + 4 * self));
+  } else {
+#pragma unroll
+    for (int q = 0; q < N; ++q) so[q] = data_off + pos[q] * colB;
+    xo = data_off + self * colB;
+  }
 }
 
 template <class S, int OP, int U>
@@ -877,7 +923,7 @@ __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int r
   tile_copy<S, OP>(a, tile, k0, klc, lds, wave, W, lane);
   const int32_t nnodes = ld_uniform(a.info + 4 * tile + 3);
   const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);
-  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
+  const uint32_t data_off = (uint32_t)nnodes * R::kBytes;   // BF16: the offset table starts here
   __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
   __syncthreads();
   // compute: node tn of the tile goes to wave tn mod W
@@ -887,23 +933,30 @@ __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int r
     uint32_t pos[R::kEntries - 1], self;
     int ne;
     tile_positions<R::kEntries>(lds, ro + R::kCoefB, pos, self, ne);
+    uint32_t so[R::kEntries - 1], xo;
     if constexpr (R::kRing2) {
       C w[R::kEntries - 1];
 #pragma unroll
       for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C));
-      if (ne <= 18) tile_node2<S, U, 18>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
-      else tile_node2<S, 1, R::kEntries - 1>(a, lds, data_off, colB, pos, self, w, obase, klc, lane);
+      if (ne <= 18) {
+        tile_offsets<S, 18>(lds, data_off, data_off, colB, pos, self, so, xo);
+        tile_node2<S, U, 18>(a, lds, so, xo, w, obase, klc, lane);
+      } else {
+        tile_offsets<S, R::kEntries - 1>(lds, data_off, data_off, colB, pos, self, so, xo);
+        tile_node2<S, 1, R::kEntries - 1>(a, lds, so, xo, w, obase, klc, lane);
+      }
     } else {
       C2 cf[7];
 #pragma unroll
       for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
       const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
+      tile_offsets<S, 7>(lds, data_off, data_off, colB, pos, self, so, xo);
       switch (ne) {
-        case 6: tile_node1<S, OP, U, 6>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-        case 5: tile_node1<S, OP, 1, 5>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-        case 7: tile_node1<S, OP, 1, 7>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-        case 4: tile_node1<S, OP, 1, 4>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
-        default: tile_node1<S, OP, 1, 3>(a, lds, data_off, colB, pos, self, cf, dg, obase, klc, lane); break;
+        case 6: tile_node1<S, OP, U, 6>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+        case 5: tile_node1<S, OP, 1, 5>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+        case 7: tile_node1<S, OP, 1, 7>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+        case 4: tile_node1<S, OP, 1, 4>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+        default: tile_node1<S, OP, 1, 3>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
       }
     }
   }
@@ -1431,7 +1484,7 @@ hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord
 Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   Shape e = sh;
   if (e.lds_tiles != 0) return e;
-  if ((dtype != DT_F32 && dtype != DT_F64) || nlev <= 32) {
+  if (nlev <= 32) {
     e.lds_tiles = 2;
     return e;
   }
@@ -1445,6 +1498,8 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   Def d;
   if (dtype == DT_F32)
     d = op == OP_LAP ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+  else if (dtype == DT_BF16)
+    d = op == OP_LAP ? Def{3, 32, 4, 0, 0, 0, 4} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else
     d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 160, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
@@ -1460,16 +1515,29 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
 
 bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
   (void)op;
-  return (dtype == DT_F32 || dtype == DT_F64) && nlev > 32 && (sh.lds_tiles == 1 || sh.lds_tiles == 3);
+  if (nlev <= 32) return false;
+  if (dtype == DT_BF16) return sh.lds_tiles == 3;   // BF16: one-tile form only
+  return (dtype == DT_F32 || dtype == DT_F64) && (sh.lds_tiles == 1 || sh.lds_tiles == 3);
 }
 
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   TileGeom g;
-  const int64_t es = dtype == DT_F64 ? 8 : 4;
+  const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
   g.ring = op == OP_LAP ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
+  if (dtype == DT_BF16) {
+    // whole columns only; per column the data, its offset-table entry and up
+    // to 8 bytes of alignment padding, plus 16 bytes of table alignment
+    g.budget -= 16;
+    const int64_t stencil = g.ring == 2 ? kLapStride : 8;
+    g.col_bytes = (int64_t)nlev * cin * es + kBf16ColExtra;
+    if (stencil * g.col_bytes + (stencil / 2) * g.row_bytes > g.budget) return g;   // KL = 0: no tiles
+    g.KL = nlev;
+    g.nchunks = 1;
+    return g;
+  }
   // Column chunk: whole columns if a tile of `want` columns (and half as many
   // nodes' table rows) fits, else the largest equal chunks that do; if even
   // that fails, fall back to the minimum of one node's stencil.
@@ -1532,11 +1600,14 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
 hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
                         void* out, const Shape& shape, int num_cus, hipStream_t stream) {
   // the tiling's LDS footprint must be the one the kernel lays out
-  const int64_t es = dtype == DT_F64 ? 8 : 4;
+  const bool bf = dtype == DT_BF16;
+  const int64_t es = dtype == DT_F64 ? 8 : bf ? 2 : 4;
   const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
-  if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || dt.lds_bytes > kLdsPerCu ||
-      dt.col_bytes != (int64_t)dt.KL * cin * es || dt.row_bytes != row)
+  const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
+  const uint32_t lds_need = dt.lds_bytes + (bf ? 16u : 0u);
+  if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || lds_need > kLdsPerCu ||
+      dt.col_bytes != colb || dt.row_bytes != row || (bf && (dt.KL != nlev || shape.lds_tiles != 3)))
     return hipErrorInvalidValue;
   TileArgs a;
   a.info = dt.info;
@@ -1554,8 +1625,9 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
     int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
     if (U > nsl) U = nsl;
     switch (dtype) {
-      case DT_F64: return launch_tiles_t<double>(op, a, U, dt.lds_bytes, shape, stream);
-      case DT_F32: return launch_tiles_t<float>(op, a, U, dt.lds_bytes, shape, stream);
+      case DT_F64: return launch_tiles_t<double>(op, a, U, lds_need, shape, stream);
+      case DT_F32: return launch_tiles_t<float>(op, a, U, lds_need, shape, stream);
+      case DT_BF16: return launch_tiles_t<bf16_t>(op, a, U, lds_need, shape, stream);
       default: return hipErrorInvalidValue;
     }
   }

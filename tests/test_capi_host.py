@@ -123,8 +123,8 @@ def test_describe_resolves_the_default_paths():
              (pa.OP_GRADIENT, pa.F64, 137, "k_tile<double, 0, 3>"),
              (pa.OP_DIVERGENCE, pa.F64, 137, "k_tile<double, 1, 3>"),
              (pa.OP_LAPLACIAN, pa.F64, 137, "k_tile<double, 4, 3>"),
-             (pa.OP_GRADIENT, pa.BF16, 137, "k_win<unsigned short, 0, 3>"),
-             (pa.OP_LAPLACIAN, pa.BF16, 137, "k_op<unsigned short, 4, 3>"),
+             (pa.OP_GRADIENT, pa.BF16, 137, "k_tile<unsigned short, 0, 3>"),
+             (pa.OP_LAPLACIAN, pa.BF16, 137, "k_tile<unsigned short, 4, 3>"),
              (pa.OP_GRADIENT, pa.F32, 19, "k_op<float, 0, 1>")]
     for op, dt, L, name in cases:
         shape, kernel = pa.describe(M, op, dt, L)

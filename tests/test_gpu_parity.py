@@ -290,3 +290,20 @@ def test_tuner_returns_a_valid_shape():
     ref = pa.gradient(M, x)
     torch.cuda.synchronize()
     assert torch.equal(tuned, ref) and torch.equal(y, ref)
+
+
+def test_bf16_unaligned_field_falls_back():
+    """BF16 tiles copy whole dwords: a field that starts 2 bytes into a dword
+    takes the row-window walk and still gives the same bits."""
+    M = gpu_mesh(32)
+    L = 137
+    x = torch.from_numpy(_input(32, L, 1, 31)).to(DEV).to(torch.bfloat16)
+    ref = pa.gradient(M, x)
+    lap_ref = pa.laplacian(M, x)
+    buf = torch.empty(M.nnodes * L + 1, dtype=torch.bfloat16, device=DEV)
+    xu = buf[1:].view(M.nnodes, L)
+    xu.copy_(x)
+    assert xu.data_ptr() % 4 == 2
+    torch.cuda.synchronize()
+    assert torch.equal(pa.gradient(M, xu), ref)
+    assert torch.equal(pa.laplacian(M, xu), lap_ref)
