@@ -1184,10 +1184,14 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
 constexpr int kConsWaves = 4;
 constexpr int kConsBlockLevels = 256;
 
-template <class S>
+template <class S, int NSL>
 __global__ __launch_bounds__(64 * kConsWaves) void k_cons_partial(const S* __restrict__ div,
                                                                   const double* __restrict__ vol, int64_t V,
                                                                   int L, int64_t chunk, double* __restrict__ part) {
+  // NSL: 64-level slices of a 256-level block that hold levels (the last
+  // block of a short column needs fewer); nodes are read four at a time and
+  // added in node order, so every sum keeps its order
+  constexpr int kNodes = 4;
   __shared__ double red[kConsWaves][kConsBlockLevels][2];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1203,17 +1207,37 @@ __global__ __launch_bounds__(64 * kConsWaves) void k_cons_partial(const S* __res
       in[r] = k < L;
       kc[r] = k < L ? k : L - 1;
     }
-    for (int64_t i = n0 + wave; i < n1; i += kConsWaves) {
+    // slices this block needs (all four unless it is the column's last)
+    const int nsl = L - kb >= kConsBlockLevels ? 4 : NSL;
+    int64_t i = n0 + wave;
+    for (; i + (kNodes - 1) * kConsWaves < n1; i += kNodes * kConsWaves) {
+      double p[kNodes][4];
+#pragma unroll
+      for (int q = 0; q < kNodes; ++q) {
+        const int64_t nd = i + q * kConsWaves;
+        const double v = vol[nd];
+        const S* col = div + nd * (int64_t)L;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[q][r] = r < nsl ? v * (double)ld1(col + kc[r]) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kNodes; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r < nsl && in[r]) {
+            s[r] += p[q][r];
+            ab[r] += fabs(p[q][r]);
+          }
+    }
+    for (; i < n1; i += kConsWaves) {
       const double v = vol[i];
       const S* col = div + i * (int64_t)L;
-      double p[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) p[r] = v * (double)ld1(col + kc[r]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (in[r]) {
-          s[r] += p[r];
-          ab[r] += fabs(p[r]);
+        if (r < nsl && in[r]) {
+          const double p = v * (double)ld1(col + kc[r]);
+          s[r] += p;
+          ab[r] += fabs(p);
         }
       }
     }
@@ -1695,19 +1719,20 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
   const int parts = conservation_parts(V, nlev);
   const int64_t chunk = (V + parts - 1) / parts;
   const dim3 g(parts), b(64 * kConsWaves);
-  switch (dtype) {
-    case DT_F64:
-      hipLaunchKernelGGL(k_cons_partial<double>, g, b, 0, stream, static_cast<const double*>(div), vol, V, nlev,
-                         chunk, scratch);
-      break;
-    case DT_F32:
-      hipLaunchKernelGGL(k_cons_partial<float>, g, b, 0, stream, static_cast<const float*>(div), vol, V, nlev,
-                         chunk, scratch);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL(k_cons_partial<bf16_t>, g, b, 0, stream, static_cast<const bf16_t*>(div), vol, V, nlev,
-                         chunk, scratch);
-      break;
+  // slices of the column's last 256-level block
+  const int rem = nlev % kConsBlockLevels;
+  const int nsl = rem == 0 ? 4 : (rem + 63) / 64;
+  switch (dtype * 4 + (nsl - 1)) {
+#define ATLAS_CONS(DT, S, N)                                                                                   \
+  case DT * 4 + (N - 1):                                                                                       \
+    hipLaunchKernelGGL((k_cons_partial<S, N>), g, b, 0, stream, static_cast<const S*>(div), vol, V, nlev, chunk, \
+                       scratch);                                                                               \
+    break;
+    ATLAS_CONS(DT_F64, double, 1) ATLAS_CONS(DT_F64, double, 2) ATLAS_CONS(DT_F64, double, 3)
+    ATLAS_CONS(DT_F64, double, 4) ATLAS_CONS(DT_F32, float, 1) ATLAS_CONS(DT_F32, float, 2)
+    ATLAS_CONS(DT_F32, float, 3) ATLAS_CONS(DT_F32, float, 4) ATLAS_CONS(DT_BF16, bf16_t, 1)
+    ATLAS_CONS(DT_BF16, bf16_t, 2) ATLAS_CONS(DT_BF16, bf16_t, 3) ATLAS_CONS(DT_BF16, bf16_t, 4)
+#undef ATLAS_CONS
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
