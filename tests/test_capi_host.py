@@ -137,3 +137,22 @@ def test_describe_resolves_the_default_paths():
     pa.set_tune(M, pa.OP_GRADIENT, pa.F32, None)
     with pytest.raises(pa.AtlasError):
         pa.describe(M, pa.OP_GRADIENT, pa.F32, 0)
+
+
+def test_tuning_cache_applies_shapes(tmp_path):
+    """A JSON cache of tuned shapes is read back and set on the mesh."""
+    from paper_1908_07038_amd import tuning
+    M = pa.Mesh("O8", device=-1)
+    path = str(tmp_path / "tune.json")
+    cache = {tuning.cache_key(M, "gradient", "float32", 137): {"shape": {"lds_tiles": 2, "row_window": 1}, "ms": 1.0},
+             tuning.cache_key(M, "laplacian", "float64", 91): {"shape": {"lds_tiles": 2}, "ms": 2.0}}
+    tuning.save_cache(path, cache)
+    back = tuning.load_cache(path)
+    assert back == cache
+    applied = tuning.apply_cache(M, back, 137)
+    assert applied == ["O8/gradient/float32/137"]
+    assert pa.describe(M, pa.OP_GRADIENT, pa.F32, 137)[1] == "k_win<float, 0, 3>"
+    assert pa.describe(M, pa.OP_LAPLACIAN, pa.F64, 137)[1].startswith("k_tile<")
+    assert tuning.apply_cache(M, back, 91, ops=["laplacian"]) == ["O8/laplacian/float64/91"]
+    assert pa.describe(M, pa.OP_LAPLACIAN, pa.F64, 91)[1] == "k_op<double, 4, 3>"
+    assert tuning.load_cache(str(tmp_path / "missing.json")) == {}
