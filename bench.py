@@ -16,7 +16,10 @@ every operator call inside the timed region; achieved bandwidth divides each
 kernel's algorithmic bytes (fields read once and written once, plus the
 minimal FP64 geometry of 104 bytes per node) by that duration.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu]
+A second, separate measurement (not in value): the O640 64-tracer batched
+plan replayed as a HIP graph, against the same work as single-field calls.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-batched]
 """
 
 import argparse
@@ -171,6 +174,76 @@ def run_gpu(args):
     return mesh, results
 
 
+def run_batched(args):
+    """O640, 64 tracers with level counts drawn from {1, 19, 60, 91, 137}:
+    gradient, divergence and both adjoints of every tracer in one persistent
+    launch per operator, replayed as a HIP graph; against the same chain as
+    single-field calls (default shapes) one tracer at a time."""
+    import torch
+
+    import paper_1908_07038_amd as pa
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    mesh = pa.Mesh("O640", radius=6371220.0, device=0)
+    V, E = mesh.nnodes, mesh.nedges
+    levels = [int(x) for x in W.batch_levels(64, 1005)]
+    need = sum(levels) * V * 4 * 7 + (4 << 30)
+    free, _ = torch.cuda.mem_get_info(dev)
+    if free < need:
+        log(f"batched: skipped, needs {need / 1e9:.0f} GB, {free / 1e9:.0f} GB free")
+        return None
+    co = mesh.coords()
+    tracers = []
+    for t, L in enumerate(levels):
+        s = W.tracer_surface(co, t, device=dev)
+        scale = 1.0 + torch.arange(L, device=dev, dtype=torch.float64) / L
+        f = (s[:, None] * scale[None, :]).float().contiguous()
+        g = torch.empty((V, L, 2), device=dev)
+        d = torch.empty((V, L), device=dev)
+        fT = torch.empty((V, L), device=dev)
+        gT = torch.empty((V, L, 2), device=dev)
+        tracers.append({"gradient": (f, g), "divergence": (g, d), "gradient_adjoint": (g, fT),
+                        "divergence_adjoint": (d, gT)})
+    torch.cuda.synchronize()
+    log(f"batched: O640 mesh and 64 tracer fields (sum of levels {sum(levels)}) in {time.time() - t0:.1f}s")
+    plan = pa.Batch(mesh, tracers)
+    reps = max(2, min(args.steps, 5))
+    plan.graph_launch()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.graph_launch()
+    b.record()
+    torch.cuda.synchronize()
+    t_graph = a.elapsed_time(b) / reps
+    a.record()
+    for _ in range(reps):
+        for tr in tracers:
+            pa.gradient(mesh, tr["gradient"][0], out=tr["gradient"][1])
+            pa.divergence(mesh, tr["divergence"][0], out=tr["divergence"][1])
+            pa.gradient_adjoint(mesh, tr["gradient_adjoint"][0], out=tr["gradient_adjoint"][1])
+            pa.divergence_adjoint(mesh, tr["divergence_adjoint"][0], out=tr["divergence_adjoint"][1])
+    b.record()
+    torch.cuda.synchronize()
+    t_single = a.elapsed_time(b) / reps
+    sl = sum(levels)
+    by = 4 * 3 * 4 * V * sl + 4 * GEOM_BYTES_PER_NODE * V * len(levels)
+    out = {"workload": "O640, 64 tracers, levels from {1,19,60,91,137} (seed 1005), FP32: grad, div, "
+                       "grad adjoint, div adjoint",
+           "sum_levels": sl, "graph_ms": round(t_graph, 3),
+           "edge_updates_s": float(f"{4 * E * sl / (t_graph * 1e-3):.4g}"),
+           "alg_GB_s": round(by / (t_graph * 1e-3) / 1e9, 1),
+           "single_field_ms": round(t_single, 3),
+           "speedup_over_single_field": round(t_single / t_graph, 3)}
+    log(f"batched: graph {t_graph:.2f} ms, single-field calls {t_single:.2f} ms")
+    del tracers, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline(grid, levels, nlev_sample, gpu_mesh_coords=None):
     """Time the FP64 oracle (as it stands) on a level sample of the same
     workload: same mesh, first `nlev_sample` levels, one full step."""
@@ -213,6 +286,7 @@ def main():
     ap.add_argument("--levels", type=int, default=137)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=2)
+    ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -242,6 +316,7 @@ def main():
             "frac": round(dbytes / (dms * 1e-3) / HBM_PEAK, 4),
             "alg_bytes_per_launch": dbytes,
             "traffic": traffic}
+    batched = None if args.skip_batched else run_batched(args)
     cpu = None
     if not args.skip_cpu:
         cpu = run_cpu_baseline(args.grid, L, args.cpu_levels)
@@ -258,6 +333,7 @@ def main():
         "fp64": {"ms_per_step": res["f64"]["ms_per_step"], "edge_updates_s": res["f64"]["edge_updates_s"]},
         "bf16": {"ms_per_step": res["bf16"]["ms_per_step"], "edge_updates_s": res["bf16"]["edge_updates_s"]},
         "f32_speedup_over_f64": round(res["f64"]["ms_per_step"] / f32["ms_per_step"], 3),
+        "batched_o640": batched,
         "detail": res,
     }
     print(json.dumps(out))

@@ -243,6 +243,10 @@ typedef struct {
                                columns when 48 (1-ring) or 96 (two-ring)
                                columns fit the budget, else equal chunks);
                                ignored if one node's stencil would not fit    */
+  int32_t batch_mode;       /* batched plans: 1 one persistent launch per
+                               operator over all tracers; 2 (the default) the
+                               single-field launch of each (operator, tracer)
+                               with the mesh's shapes, operators outermost    */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;
@@ -256,13 +260,18 @@ int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* 
                        int32_t ntracers, uint32_t op_mask, const atlas_tune_t* tune,
                        atlas_batch_t* out);
 
-/* Enqueue one persistent launch per selected operator (in the order of the
- * bits above) on `stream`.  Allocates nothing and never synchronises, so it
- * may be recorded into a HIP graph by stream capture. */
+/* Enqueue the plan's work on `stream`, operators in the order of the bits
+ * above: with batch_mode 1 one persistent launch per operator; otherwise the
+ * single-field launch of every tracer for each operator.  The persistent form
+ * allocates nothing and never synchronises; the field form does so only the
+ * first time a (operator, dtype, level count) is used on the mesh, when it
+ * builds node orders, tilings and records -- after one eager run it too may be
+ * recorded into a HIP graph by stream capture. */
 int atlas_batch_run(atlas_batch_t plan, void* stream);
 
 /* Run the plan through a HIP graph owned by the plan: the first call
- * captures atlas_batch_run on `stream` and instantiates the graph, every
+ * (after one eager run on `stream` in the field form, then synchronising
+ * `stream`) captures atlas_batch_run and instantiates the graph, every
  * call launches it on `stream`. */
 int atlas_batch_graph_launch(atlas_batch_t plan, void* stream);
 

@@ -250,6 +250,7 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->producer_waves = s.producer_waves;
   t->tile_wgs_per_cu = s.tile_wgs_per_cu;
   t->tile_levels = s.tile_levels;
+  t->batch_mode = s.batch_mode;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -297,6 +298,8 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.tile_wgs_per_cu = t->tile_wgs_per_cu;
   if (t->tile_levels < 0) return fail(ATLAS_EINVAL, "tile_levels must be >= 0");
   s.tile_levels = t->tile_levels;
+  if (t->batch_mode < 0 || t->batch_mode > 2) return fail(ATLAS_EINVAL, "batch_mode must be 0, 1 or 2");
+  s.batch_mode = t->batch_mode;
 
   return ATLAS_OK;
 }
@@ -798,8 +801,23 @@ int plan_upload(atlas_batch_s* b) {
   return ATLAS_OK;
 }
 
+// Persistent form: one launch per operator over every tracer.  Field form
+// (the default): the single-field launch of each (operator, tracer), with the
+// mesh's shapes, operators outermost -- the same order of work.
+bool plan_persistent(const Shape& sh) { return sh.batch_mode == 1; }
+
 int plan_run(atlas_batch_s* b, hipStream_t st, const Shape& sh) {
   const int64_t V = b->mesh->host.V;
+  if (!plan_persistent(sh)) {
+    for (int o = 0; o < 4; ++o) {
+      if (!(b->mask & (1u << o))) continue;
+      for (const atlas_tracer_desc_t& d : b->descs) {
+        int rc = run_op(b->mesh, o, b->dtype, d.nlev, d.in[o], d.out[o], st);
+        if (rc) return rc;
+      }
+    }
+    return ATLAS_OK;
+  }
   for (int o = 0; o < 4; ++o) {
     if (!(b->mask & (1u << o))) continue;
     hipError_t e = launch_batched(o, b->dtype, b->mesh->tables(b->dtype), b->order, V, b->items[o],
@@ -877,6 +895,15 @@ int atlas_batch_graph_launch(atlas_batch_t plan, void* stream) {
       e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
     }
+    if (!plan_persistent(plan->shape)) {
+      // one eager pass, in order on the caller's stream, builds every node
+      // order, tiling and record table the launches need (host work and
+      // allocation cannot be captured)
+      int rc0 = plan_run(plan, (hipStream_t)stream, plan->shape);
+      if (rc0) return rc0;
+      e = hipStreamSynchronize((hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
     e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     int rc = plan_run(plan, plan->capture_stream, plan->shape);
@@ -921,29 +948,42 @@ int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_
   const int wpbs[] = {2, 4};
   const int npws[] = {1, 2, 4};
   const int bpcs[] = {2, 4, 8};
-  for (int w : wpbs)
-    for (int n : npws)
-      for (int c : bpcs)
-        for (int x = 0; x < 2; ++x) {
-          Shape s;
-          s.waves_per_block = w;
-          s.nodes_per_wave = n;
-          s.blocks_per_cu = c;
-          s.xcd_remap = x;
-          plan->shape = s;
-          if (hipStreamSynchronize(st) != hipSuccess) { rc = fail(ATLAS_EHIP, "hipStreamSynchronize"); goto done; }
-          if ((rc = plan_upload(plan))) goto done;
-          if ((rc = plan_run(plan, st, s))) goto done;
-          (void)hipEventRecord(e0, st);
-          for (int r = 0; r < reps; ++r)
-            if ((rc = plan_run(plan, st, s))) goto done;
-          (void)hipEventRecord(e1, st);
-          if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ATLAS_EHIP, "hipEventSynchronize"); goto done; }
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          ms /= (float)reps;
-          if (ms < bestt) { bestt = ms; bs = s; }
-        }
+  // the field form first (its launches use the mesh's shapes), then the
+  // persistent form over workgroup shapes
+  for (int k = -1; k < 2 * 3 * 3 * 2; ++k) {
+    Shape s;
+    if (k < 0) {
+      s.batch_mode = 2;
+    } else {
+      s.batch_mode = 1;
+      s.waves_per_block = wpbs[k / 18];
+      s.nodes_per_wave = npws[(k / 6) % 3];
+      s.blocks_per_cu = bpcs[(k / 2) % 3];
+      s.xcd_remap = k % 2;
+    }
+    plan->shape = s;
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(ATLAS_EHIP, "hipStreamSynchronize");
+      goto done;
+    }
+    if ((rc = plan_upload(plan))) goto done;
+    if ((rc = plan_run(plan, st, s))) goto done;
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r)
+      if ((rc = plan_run(plan, st, s))) goto done;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(ATLAS_EHIP, "hipEventSynchronize");
+      goto done;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (ms < bestt) {
+      bestt = ms;
+      bs = s;
+    }
+  }
   shape_out(bs, best);
   if (best_ms) *best_ms = bestt;
 done:

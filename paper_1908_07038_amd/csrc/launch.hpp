@@ -39,6 +39,7 @@ struct Shape {
   int producer_waves = 0;    // 0: 2; producer (copy) waves per persistent tile workgroup
   int tile_wgs_per_cu = 0;   // 0: 1; persistent tile workgroups per CU
   int tile_levels = 0;       // 0: automatic; else levels per column chunk of a tile
+  int batch_mode = 0;        // batched plans: 0 default (field launches), 1 persistent, 2 field launches
 };
 
 constexpr int kDefaultBandRows = 32;

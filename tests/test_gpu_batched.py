@@ -40,22 +40,27 @@ def _check_against_single(mesh, tracers):
             assert torch.equal(y, ref), (name, x.shape)
 
 
+MODES = {"fields": None, "persistent": {"batch_mode": 1}}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_batched_equals_single(dtype):
+def test_batched_equals_single(dtype, mode):
     M = pa.Mesh("O32", device=0)
     levels = [1, 19, 60, 91, 137, 137, 5, 33, 2, 64]
     tracers = _tracers(M, levels, dtype, 1)
-    plan = pa.Batch(M, tracers)
+    plan = pa.Batch(M, tracers, tune=MODES[mode])
     plan.run()
     torch.cuda.synchronize()
     _check_against_single(M, tracers)
 
 
-def test_graph_replays_equal_eager():
+@pytest.mark.parametrize("mode", list(MODES))
+def test_graph_replays_equal_eager(mode):
     M = pa.Mesh("O32", device=0)
     levels = [137, 1, 60, 19, 91]
     tracers = _tracers(M, levels, torch.float32, 2)
-    plan = pa.Batch(M, tracers)
+    plan = pa.Batch(M, tracers, tune=MODES[mode])
     for rep in range(3):
         for tr in tracers:                       # eager work between replays
             for _, (x, y) in tr.items():
@@ -82,12 +87,13 @@ def test_batch_tune_keeps_results():
     _check_against_single(M, tracers)
 
 
-def test_batched_against_oracle():
+@pytest.mark.parametrize("mode", list(MODES))
+def test_batched_against_oracle(mode):
     M = pa.Mesh("O8", device=0)
     m, g = mesh_and_dual(8)
     levels = [3, 40, 1]
     tracers = _tracers(M, levels, torch.float64, 4)
-    pa.Batch(M, tracers).run()
+    pa.Batch(M, tracers, tune=MODES[mode]).run()
     torch.cuda.synchronize()
     ora = {"gradient": nabla.gradient, "divergence": nabla.divergence,
            "gradient_adjoint": nabla.gradient_adjoint, "divergence_adjoint": nabla.divergence_adjoint}
