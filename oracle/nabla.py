@@ -14,7 +14,14 @@ finite-volume form used here is:
 * divergence: div_i = (1/V_i) sum_{e at i} sign(i,e) 0.5 (U_a + U_b) . S_e,
   with U_j = u_j east_j + v_j north_j.
 * Laplacian:  lap = div(grad f).
-* adjoints: the exact transposes of gradient and divergence for the plain
+* curl:       curl_i = (1/V_i) sum_{e at i} sign(i,e) 0.5 (U_a + U_b) . T_e with
+  T_e = m_e x S_e, m_e the unit edge midpoint: the dual face conormal turned
+  by a right angle about the local vertical, so the sum is the circulation of
+  U around the cell, counter-clockwise seen from outside (Stokes), divided by
+  the cell area -- the vertical component of the vorticity.  The paper names
+  curl next to gradient and divergence (Section 2.3); this is the same
+  edge-based form with the tangential instead of the normal face flux.
+* adjoints: the exact transposes of gradient, divergence and curl for the plain
   Euclidean inner product over every (node, level, component) entry,
   evaluated as transposed edge scatters.
 * conservation: per level, sum_i V_i div_ik and sum_i |V_i div_ik| in FP64
@@ -110,6 +117,45 @@ def divergence(mesh, geom, uv):
         U = _to_cartesian(geom, uv[:, k0:k1])              # [V, Lb, 3]
         flux = 0.5 * np.einsum("ekc,ec->ek", U[a] + U[b], geom.S)
         out[:, k0:k1] = (_scatter(a, flux, V) - _scatter(b, flux, V)) / geom.V[:, None]
+    return out
+
+
+def face_tangents(geom):
+    """T_e = m_e x S_e: [E][3]."""
+    return np.cross(geom.m, geom.S)
+
+
+def curl(mesh, geom, uv):
+    """curl (u, v): [V][L][2] -> [V][L], per metre (vertical vorticity)."""
+    uv = _check_vector(mesh, uv)
+    V, L, _ = uv.shape
+    a, b = mesh.edges[:, 0], mesh.edges[:, 1]
+    T = face_tangents(geom)
+    out = np.empty((V, L))
+    for k0, k1 in _blocks(L):
+        U = _to_cartesian(geom, uv[:, k0:k1])              # [V, Lb, 3]
+        flux = 0.5 * np.einsum("ekc,ec->ek", U[a] + U[b], T)
+        out[:, k0:k1] = (_scatter(a, flux, V) - _scatter(b, flux, V)) / geom.V[:, None]
+    return out
+
+
+def curl_adjoint(mesh, geom, z):
+    """Transpose of :func:`curl`: [V][L] -> [V][L][2] (as the divergence
+    adjoint, with T_e in place of S_e)."""
+    z = _check_scalar(mesh, z)
+    V, L = z.shape
+    a, b = mesh.edges[:, 0], mesh.edges[:, 1]
+    T = face_tangents(geom)
+    out = np.empty((V, L, 2))
+    for k0, k1 in _blocks(L):
+        q = z[:, k0:k1] / geom.V[:, None]
+        h = 0.5 * (q[a] - q[b])                              # [E, Lb]
+        H = np.empty((V, k1 - k0, 3))
+        for c in range(3):
+            vals = h * T[:, c][:, None]
+            H[:, :, c] = _scatter(a, vals, V) + _scatter(b, vals, V)
+        out[:, k0:k1, 0] = np.einsum("vkc,vc->vk", H, geom.east)
+        out[:, k0:k1, 1] = np.einsum("vkc,vc->vk", H, geom.north)
     return out
 
 
@@ -218,6 +264,20 @@ def divergence_at(mesh, geom, get, nodes):
     Ua = _to_cartesian(geom, get(a), a)
     Ub = _to_cartesian(geom, get(b), b)
     flux = 0.5 * np.einsum("ekc,ec->ek", Ua + Ub, geom.S[eids])
+    n = nodes.size
+    out = (_local_scatter(lut, a, flux, n) - _local_scatter(lut, b, flux, n))
+    return nodes, out / geom.V[nodes][:, None]
+
+
+def curl_at(mesh, geom, get, nodes):
+    """curl at ``nodes``; ``get`` returns [m][L][2] rows."""
+    nodes, eids = _incident(mesh, nodes)
+    lut = _lut(mesh, nodes)
+    a, b = mesh.edges[eids, 0], mesh.edges[eids, 1]
+    Ua = _to_cartesian(geom, get(a), a)
+    Ub = _to_cartesian(geom, get(b), b)
+    T = np.cross(geom.m[eids], geom.S[eids])
+    flux = 0.5 * np.einsum("ekc,ec->ek", Ua + Ub, T)
     n = nodes.size
     out = (_local_scatter(lut, a, flux, n) - _local_scatter(lut, b, flux, n))
     return nodes, out / geom.V[nodes][:, None]

@@ -53,7 +53,7 @@ def test_closure_is_nearly_radial():
 # ------------------------------------------- independent cell construction
 
 def _ring_walk_operators(m, R):
-    """Dense gradient and divergence matrices built cell by cell.
+    """Dense gradient, divergence and curl matrices built cell by cell.
 
     For every node the median cell boundary is walked counter-clockwise
     (seen from outside) through its triangles T = (i, j, k):
@@ -67,6 +67,7 @@ def _ring_walk_operators(m, R):
     mid = lambda i, j: (X[i] + X[j]) / np.linalg.norm(X[i] + X[j])  # noqa: E731
     G = np.zeros((V, 3, V))
     D = np.zeros((V, V, 3))
+    K = np.zeros((V, V, 3))
     area = np.zeros(V)
     east = np.stack([-m.grid.sinlon, m.grid.coslon, 0 * m.grid.lon], 1)
     north = np.stack([-m.grid.sinlat * m.grid.coslon, -m.grid.sinlat * m.grid.sinlon,
@@ -79,7 +80,7 @@ def _ring_walk_operators(m, R):
             mij, mik = mid(i, j), mid(i, k)
             area[i] += (solid_angle(X[i][None], mij[None], mik[None])[0] +
                         solid_angle(mij[None], c[None], mik[None])[0])
-            for (p, q, nb) in [(mij, c, j), (c, mik, k)]:
+            for (p, q, nb, mf) in [(mij, c, j, mij), (c, mik, k, mik)]:
                 w = np.cross(q, p)
                 ang = math.atan2(np.linalg.norm(w), p @ q)
                 nu = R * ang * w / np.linalg.norm(w)
@@ -88,6 +89,11 @@ def _ring_walk_operators(m, R):
                 G[i, :, nb] += 0.5 * nu
                 D[i, i, :] += 0.5 * nu
                 D[i, nb, :] += 0.5 * nu
+                # circulation: the arc's conormal turned about its face's
+                # midpoint direction
+                tau = np.cross(mf, nu)
+                K[i, i, :] += 0.5 * tau
+                K[i, nb, :] += 0.5 * tau
     vol = R * R * area
     Gm = np.zeros((V, 2, V))
     Gm[:, 0, :] = np.einsum("vcx,vc->vx", G, east) / vol[:, None]
@@ -95,7 +101,10 @@ def _ring_walk_operators(m, R):
     Dm = np.zeros((V, V, 2))
     Dm[:, :, 0] = np.einsum("vxc,xc->vx", D, east) / vol[:, None]
     Dm[:, :, 1] = np.einsum("vxc,xc->vx", D, north) / vol[:, None]
-    return Gm, Dm, vol
+    Km = np.zeros((V, V, 2))
+    Km[:, :, 0] = np.einsum("vxc,xc->vx", K, east) / vol[:, None]
+    Km[:, :, 1] = np.einsum("vxc,xc->vx", K, north) / vol[:, None]
+    return Gm, Dm, vol, Km
 
 
 @pytest.fixture(scope="module")
@@ -105,12 +114,12 @@ def o4_brute():
 
 
 def test_o4_volumes_brute_force(o4_brute):
-    m, g, (_, _, vol) = o4_brute
+    m, g, (_, _, vol, _) = o4_brute
     np.testing.assert_allclose(g.V, vol, rtol=1e-13)
 
 
 def test_o4_gradient_brute_force(o4_brute):
-    m, g, (Gm, _, _) = o4_brute
+    m, g, (Gm, _, _, _) = o4_brute
     V = m.nnodes
     eye = np.eye(V)
     G = nabla.gradient(m, g, eye)                       # [V][V][2]
@@ -122,7 +131,7 @@ def test_o4_gradient_brute_force(o4_brute):
 
 
 def test_o4_divergence_brute_force(o4_brute):
-    m, g, (_, Dm, _) = o4_brute
+    m, g, (_, Dm, _, _) = o4_brute
     V = m.nnodes
     scale = np.abs(Dm).max()
     for comp in range(2):
@@ -133,7 +142,7 @@ def test_o4_divergence_brute_force(o4_brute):
 
 
 def test_o4_adjoints_are_dense_transposes(o4_brute):
-    m, g, (Gm, Dm, _) = o4_brute
+    m, g, (Gm, Dm, _, Km) = o4_brute
     V = m.nnodes
     # G as a (2V x V) matrix, rows (node, comp)
     Gmat = Gm.transpose(0, 1, 2).reshape(2 * V, V)
@@ -146,6 +155,19 @@ def test_o4_adjoints_are_dense_transposes(o4_brute):
     # (D^T e_i)_(j, c) = D[i, (j, c)]
     np.testing.assert_allclose(DT, Dm.transpose(1, 0, 2), rtol=0,
                                atol=1e-13 * np.abs(Dm).max())
+    KT = nabla.curl_adjoint(m, g, np.eye(V))
+    np.testing.assert_allclose(KT, Km.transpose(1, 0, 2), rtol=0, atol=1e-13 * np.abs(Km).max())
+
+
+def test_o4_curl_brute_force(o4_brute):
+    m, g, (_, _, _, Km) = o4_brute
+    V = m.nnodes
+    scale = np.abs(Km).max()
+    for comp in range(2):
+        uv = np.zeros((V, V, 2))
+        uv[np.arange(V), np.arange(V), comp] = 1.0
+        K = nabla.curl(m, g, uv)
+        np.testing.assert_allclose(K, Km[:, :, comp], rtol=0, atol=1e-13 * scale)
 
 
 # ------------------------------------------------------------ invariants
@@ -234,6 +256,75 @@ def test_laplacian_of_spherical_harmonics_converges():
     assert res[128][0][0] < 6e-3
 
 
+def _rotation_field(gr, axis):
+    """Solid-body rotation U = axis x r (unit angular speed, R = radius) as
+    (east, north) components: its vertical vorticity is 2 axis . r_hat."""
+    rhat = np.stack([gr.coslat * gr.coslon, gr.coslat * gr.sinlon, gr.sinlat], 1)
+    east = np.stack([-gr.sinlon, gr.coslon, 0 * gr.lon], 1)
+    north = np.stack([-gr.sinlat * gr.coslon, -gr.sinlat * gr.sinlon, gr.coslat], 1)
+    U = R * np.cross(np.asarray(axis, dtype=float)[None, :], rhat)
+    uv = np.stack([np.sum(U * east, 1), np.sum(U * north, 1)], 1)[:, None, :]
+    return uv, 2.0 * rhat @ np.asarray(axis, dtype=float)
+
+
+def test_curl_of_solid_body_rotation_converges():
+    """Rotation about the polar axis (u = R cos(lat), v = 0) and about the x
+    axis: curl = 2 axis . r_hat.  Measured orders from O16 to O64: L-inf 1.0;
+    L2 away from the caps and quadrant meridians 2.1 (polar axis) and 1.4-1.5
+    (x axis, whose flow crosses the zipper rows)."""
+    res = {}
+    for N in [16, 32, 64]:
+        m, g = mesh_and_dual(N)
+        k = _masked(m)
+        row = []
+        for axis in [(0, 0, 1), (1, 0, 0)]:
+            uv, ex = _rotation_field(m.grid, axis)
+            z = nabla.curl(m, g, uv)[:, 0]
+            err = z - ex
+            row.append((math.sqrt(np.sum(g.V[k] * err[k] ** 2) / np.sum(g.V[k] * ex[k] ** 2)),
+                        np.abs(err).max() / 2.0))
+        res[N] = row
+    for q, l2_order in [(0, 1.9), (1, 1.3)]:
+        assert res[64][q][0] < 1e-3, res[64][q]
+        for a, b in [(16, 32), (32, 64)]:
+            assert math.log2(res[a][q][0] / res[b][q][0]) > l2_order, (q, a, b, res)
+            assert math.log2(res[a][q][1] / res[b][q][1]) > 0.9, (q, a, b, res)
+
+
+@pytest.mark.parametrize("N", [4, 32])
+def test_curl_circulation_sums_to_zero(N):
+    """Each dual face is shared by two cells with opposite orientation, so
+    the area-weighted curl sums to zero over the closed sphere."""
+    m, g = mesh_and_dual(N)
+    uv = W.normal((m.nnodes, 4, 2), 17)
+    z = nabla.curl(m, g, uv)
+    prod = g.V[:, None] * z
+    assert np.all(np.abs(prod.sum(0)) <= 1e-14 * np.abs(prod).sum(0))
+
+
+def test_curl_of_gradient_converges_to_zero():
+    """curl(grad f) of a smooth f vanishes in the limit (not exactly on the
+    discrete dual): it shrinks with resolution relative to |grad f| / R."""
+    res = {}
+    for N in [16, 32, 64]:
+        m, g = mesh_and_dual(N)
+        f = W.real_sh(3, 1, coords(m))[:, None]
+        gr_ = nabla.gradient(m, g, f)
+        z = nabla.curl(m, g, gr_)[:, 0]
+        k = _masked(m)
+        res[N] = math.sqrt(np.sum(g.V[k] * z[k] ** 2) / np.sum(g.V[k])) * R / np.abs(gr_).max()
+    assert res[64] < res[32] < res[16], res
+
+
+def test_curl_at_equals_full_scatter():
+    m, g = mesh_and_dual(16)
+    uv = W.normal((m.nnodes, 3, 2), 19)
+    nodes = np.array([0, 5, 17, 100, m.nnodes // 2, m.nnodes - 1])
+    idx, z = nabla.curl_at(m, g, lambda i: uv[i], nodes)
+    full = nabla.curl(m, g, uv)
+    np.testing.assert_allclose(z, full[idx], rtol=0, atol=1e-15 * np.abs(full).max())
+
+
 def test_spherical_harmonics_are_orthonormal():
     m, g = mesh_and_dual(64)
     co = coords(m)
@@ -253,6 +344,10 @@ def test_dot_product_tests(N):
     lhs = np.sum(nabla.gradient(m, g, x) * y)
     rhs = np.sum(x * nabla.gradient_adjoint(m, g, y))
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    cy = nabla.curl(m, g, y)
+    lhs = np.sum(cy * x)
+    rhs = np.sum(y * nabla.curl_adjoint(m, g, x))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(cy) * np.linalg.norm(x)
     lhs = np.sum(nabla.divergence(m, g, y) * x)
     rhs = np.sum(y * nabla.divergence_adjoint(m, g, x))
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
