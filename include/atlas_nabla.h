@@ -168,6 +168,20 @@ int atlas_nabla_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
 int atlas_nabla_divergence_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
                                    const void* d, void* uvbar, void* stream);
 
+/* Curl (vertical vorticity), the fourth operation Section 2.3 names, in the
+ * same edge-based form with the tangential face vector:
+ * curl_i = (1/V_i) sum_e sign(i,e) 0.5 (U_i + U_j) . T_e, T_e = m_e x S_e,
+ * m_e the unit edge midpoint, U = u east + v north -- the circulation around
+ * the dual cell, counter-clockwise seen from outside, per unit area.
+ * uv: vector [V][nlev][2] -> zeta: scalar [V][nlev] (per metre). */
+int atlas_nabla_curl(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                     const void* uv, void* zeta, void* stream);
+
+/* Exact transpose of atlas_nabla_curl.
+ * z: scalar [V][nlev] -> uvbar: vector [V][nlev][2]. */
+int atlas_nabla_curl_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                             const void* z, void* uvbar, void* stream);
+
 /* Global conservation check of a divergence field: per level k,
  * out_sum[k] = sum_i V_i div_ik and out_abs[k] = sum_i |V_i div_ik|, both
  * accumulated in FP64 in a fixed order (two-pass tree), so results are
@@ -188,7 +202,9 @@ enum {
   ATLAS_OP_DIVERGENCE = 2,
   ATLAS_OP_GRADIENT_ADJOINT = 4,
   ATLAS_OP_DIVERGENCE_ADJOINT = 8,
-  ATLAS_OP_LAPLACIAN = 16   /* tuning and launch shapes only; not batchable */
+  ATLAS_OP_LAPLACIAN = 16,  /* tuning and launch shapes only; not batchable */
+  ATLAS_OP_CURL = 32,       /* tuning and launch shapes only; not batchable */
+  ATLAS_OP_CURL_ADJOINT = 64 /* tuning and launch shapes only; not batchable */
 };
 
 typedef struct {

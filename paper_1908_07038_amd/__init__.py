@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libatlas_nabla.so")
 
 F64, F32, BF16 = 0, 1, 2
 OP_GRADIENT, OP_DIVERGENCE, OP_GRADIENT_ADJOINT, OP_DIVERGENCE_ADJOINT, OP_LAPLACIAN = 1, 2, 4, 8, 16
+OP_CURL, OP_CURL_ADJOINT = 32, 64
 STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EHIP",
           -4: "ATLAS_ENODEV", -5: "ATLAS_EDTYPE", -6: "ATLAS_ESHAPE"}
 
@@ -81,6 +82,8 @@ _SIGS = {
     "atlas_nabla_gradient_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_divergence_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_conservation": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_nabla_curl_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_batch_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TracerDesc), _I32,
                                           ctypes.c_uint32, ctypes.POINTER(TuneShape), ctypes.POINTER(_P)]),
     "atlas_batch_run": (ctypes.c_int, [_P, _P]),
@@ -278,6 +281,16 @@ def divergence_adjoint(mesh, d, out=None):
     return _apply(lib().atlas_nabla_divergence_adjoint, mesh, d, 1, 2, out)
 
 
+def curl(mesh, uv, out=None):
+    """[V][L][2] -> [V][L]: vertical vorticity (circulation per unit area)."""
+    return _apply(lib().atlas_nabla_curl, mesh, uv, 2, 1, out)
+
+
+def curl_adjoint(mesh, z, out=None):
+    """[V][L] -> [V][L][2], exact transpose of :func:`curl`."""
+    return _apply(lib().atlas_nabla_curl_adjoint, mesh, z, 1, 2, out)
+
+
 def laplacian(mesh, f, out=None, workspace=None):
     """div(grad f): fused two-ring pass, or two passes through ``workspace``
     ([V][L][2], same dtype) when given."""
@@ -333,5 +346,5 @@ def set_tune(mesh, op, dtype_code, shape=None):
         _check(lib().atlas_nabla_set_tune(mesh.handle, dtype_code, op, ctypes.byref(ts)))
 
 
-from .autograd import Gradient, Divergence, Laplacian, grad, div, lap  # noqa: E402,F401
+from .autograd import Gradient, Divergence, Laplacian, Curl, grad, div, lap, rot  # noqa: E402,F401
 from .batch import Batch  # noqa: E402,F401

@@ -186,8 +186,9 @@ void upload_tables(atlas_mesh_s& m) {
   m.tab64.nbr8 = m.tab32.nbr8 = nbr8;
   m.tab64.lap_nbr = m.tab32.lap_nbr = lap_nbr;
   m.tab64.lap_stride = m.tab32.lap_stride = t.lap_stride;
-  const std::vector<double>* src[4] = {&t.grad, &t.div, &t.gradT, &t.divT};
-  for (int o = 0; o < 4; ++o) {
+  const std::vector<double>* src[OP_COUNT] = {&t.grad, &t.div, &t.gradT, &t.divT, nullptr, &t.curl, &t.curlT};
+  for (int o = 0; o < OP_COUNT; ++o) {
+    if (!src[o]) continue;
     m.tab64.coef[o] = m.upload(*src[o]);
     m.tab32.coef[o] = m.upload(to_f32(*src[o]));
   }
@@ -211,14 +212,17 @@ int op_from_bit(uint32_t bit) {
     case ATLAS_OP_GRADIENT_ADJOINT: return OP_GRADT;
     case ATLAS_OP_DIVERGENCE_ADJOINT: return OP_DIVT;
     case ATLAS_OP_LAPLACIAN: return OP_LAP;
+    case ATLAS_OP_CURL: return OP_CURL;
+    case ATLAS_OP_CURL_ADJOINT: return OP_CURLT;
     default: return -1;
   }
 }
 
 // components of the input and output fields of each operator
-const int kInComps[OP_COUNT] = {1, 2, 2, 1, 1};
-const int kOutComps[OP_COUNT] = {2, 1, 1, 2, 1};
-const char* kOpName[OP_COUNT] = {"gradient", "divergence", "gradient_adjoint", "divergence_adjoint", "laplacian"};
+const int kInComps[OP_COUNT] = {1, 2, 2, 1, 1, 2, 1};
+const int kOutComps[OP_COUNT] = {2, 1, 1, 2, 1, 1, 2};
+const char* kOpName[OP_COUNT] = {"gradient", "divergence", "gradient_adjoint", "divergence_adjoint", "laplacian",
+                                 "curl", "curl_adjoint"};
 
 int check_mesh_device(atlas_mesh_t mesh) {
   if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
@@ -497,6 +501,14 @@ int atlas_nabla_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, con
 int atlas_nabla_divergence_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* d, void* uvbar,
                                    void* stream) {
   return run_op(mesh, OP_DIVT, dtype, nlev, d, uvbar, stream);
+}
+
+int atlas_nabla_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* zeta, void* stream) {
+  return run_op(mesh, OP_CURL, dtype, nlev, uv, zeta, stream);
+}
+
+int atlas_nabla_curl_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* z, void* uvbar, void* stream) {
+  return run_op(mesh, OP_CURLT, dtype, nlev, z, uvbar, stream);
 }
 
 int atlas_nabla_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* f, void* lap, void* workspace,

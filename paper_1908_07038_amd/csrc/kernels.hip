@@ -1498,9 +1498,9 @@ hipError_t launch_op(int op, int dtype, const DevTables& t, const NodeOrder& ord
   const int U = window ? window_slices(nlev, shape) : slices_per_iter(nlev, shape);
   const int64_t nblocks = blocks_for(op, ord, V, nlev, shape);
   switch (dtype) {
-    case DT_F64: return launch_op_t<double>(op, a, U, nblocks, window, shape, stream);
-    case DT_F32: return launch_op_t<float>(op, a, U, nblocks, window, shape, stream);
-    case DT_BF16: return launch_op_t<bf16_t>(op, a, U, nblocks, window, shape, stream);
+    case DT_F64: return launch_op_t<double>(kernel_op(op), a, U, nblocks, window, shape, stream);
+    case DT_F32: return launch_op_t<float>(kernel_op(op), a, U, nblocks, window, shape, stream);
+    case DT_BF16: return launch_op_t<bf16_t>(kernel_op(op), a, U, nblocks, window, shape, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1518,7 +1518,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   // (mode, KiB, tile rows, computing waves, copying waves, lanes per node,
   // waves per workgroup of the one-tile form)
   struct Def { int mode, kb, rows, cw, pw, lanes, wpb; };
-  const bool vec_in = op == OP_DIV || op == OP_GRADT;
+  const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT;
   Def d;
   if (dtype == DT_F32)
     d = op == OP_LAP ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
@@ -1547,7 +1547,7 @@ bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   TileGeom g;
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
-  const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
   g.ring = op == OP_LAP ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
@@ -1626,7 +1626,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   // the tiling's LDS footprint must be the one the kernel lays out
   const bool bf = dtype == DT_BF16;
   const int64_t es = dtype == DT_F64 ? 8 : bf ? 2 : 4;
-  const int64_t cin = (op == OP_DIV || op == OP_GRADT) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
   const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
   const uint32_t lds_need = dt.lds_bytes + (bf ? 16u : 0u);
@@ -1649,9 +1649,9 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
     int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
     if (U > nsl) U = nsl;
     switch (dtype) {
-      case DT_F64: return launch_tiles_t<double>(op, a, U, lds_need, shape, stream);
-      case DT_F32: return launch_tiles_t<float>(op, a, U, lds_need, shape, stream);
-      case DT_BF16: return launch_tiles_t<bf16_t>(op, a, U, lds_need, shape, stream);
+      case DT_F64: return launch_tiles_t<double>(kernel_op(op), a, U, lds_need, shape, stream);
+      case DT_F32: return launch_tiles_t<float>(kernel_op(op), a, U, lds_need, shape, stream);
+      case DT_BF16: return launch_tiles_t<bf16_t>(kernel_op(op), a, U, lds_need, shape, stream);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1669,8 +1669,10 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
   if (U > nsl) U = nsl;
   switch (dtype) {
-    case DT_F64: return launch_tiles2_t<double>(op, a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
-    case DT_F32: return launch_tiles2_t<float>(op, a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
+    case DT_F64:
+      return launch_tiles2_t<double>(kernel_op(op), a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
+    case DT_F32:
+      return launch_tiles2_t<float>(kernel_op(op), a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1698,7 +1700,7 @@ void kernel_label(int op, int dtype, int nlev, const Shape& sh, char* buf, int l
       U = slices_per_iter(nlev, sh);
     }
   }
-  snprintf(buf, (size_t)len, "%s<%s, %d, %d>", name, ty, op, U);
+  snprintf(buf, (size_t)len, "%s<%s, %d, %d>", name, ty, kernel_op(op), U);
 }
 
 int window_slices(int nlev, const Shape& sh) {

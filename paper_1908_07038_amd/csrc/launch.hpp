@@ -7,14 +7,20 @@
 
 namespace atlasnabla {
 
-enum Op : int { OP_GRAD = 0, OP_DIV = 1, OP_GRADT = 2, OP_DIVT = 3, OP_LAP = 4, OP_COUNT = 5 };
+// OP_CURL and OP_CURLT run the divergence and divergence-adjoint kernels on
+// their own coefficient tables (the curl is the divergence form with the
+// tangential face vector).
+enum Op : int { OP_GRAD = 0, OP_DIV = 1, OP_GRADT = 2, OP_DIVT = 3, OP_LAP = 4, OP_CURL = 5, OP_CURLT = 6,
+                OP_COUNT = 7 };
+// Kernel template an operator runs with.
+inline int kernel_op(int op) { return op == OP_CURL ? OP_DIV : op == OP_CURLT ? OP_DIVT : op; }
 enum Dtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 
 // Device tables of one mesh for one coefficient precision (FP64 for DT_F64,
 // FP32 for DT_F32 and DT_BF16).
 struct DevTables {
   const int32_t* nbr8 = nullptr;        // [V][8]
-  const void* coef[4] = {};             // grad, div, gradT, divT: [V][8] pairs
+  const void* coef[OP_COUNT] = {};      // per Op (none for OP_LAP): [V][8] pairs
   const int32_t* lap_nbr = nullptr;     // [V][lap_stride]
   const void* lap_w = nullptr;          // [V][lap_stride]
   int lap_stride = 0;

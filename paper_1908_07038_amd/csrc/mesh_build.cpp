@@ -422,6 +422,18 @@ int window_meta(const HostMesh& m, int64_t i, int deg) {
   return cu | (1 << 8);
 }
 
+// T_e = m_e x S_e, m_e the unit midpoint of edge e (normalised endpoint sum,
+// evaluated as for the dual faces): the dual face conormal turned by a right
+// angle about the local vertical, the tangential face flux of the curl.
+static V3 face_tangent(const HostMesh& m, int64_t e, const V3& S) {
+  const int64_t a = m.edges[2 * e], b = m.edges[2 * e + 1];
+  const double x = m.xyz[3 * a] + m.xyz[3 * b], y = m.xyz[3 * a + 1] + m.xyz[3 * b + 1],
+               z = m.xyz[3 * a + 2] + m.xyz[3 * b + 2];
+  const double nrm = std::sqrt((x * x + y * y) + z * z);
+  const double mx = x / nrm, my = y / nrm, mz = z / nrm;
+  return {my * S[2] - mz * S[1], mz * S[0] - mx * S[2], mx * S[1] - my * S[0]};
+}
+
 // Per-slot coefficients (difference / gather form of the edge sums):
 //   a_is = 0.5 sign (east_i . S_e) / V_i     b_is = 0.5 sign (north_i . S_e) / V_i
 //   c_is = 0.5 sign (east_n . S_e) / V_i     d_is = 0.5 sign (north_n . S_e) / V_i
@@ -430,6 +442,8 @@ int window_meta(const HostMesh& m, int64_t i, int deg) {
 //   div_i   = A_i u_i + B_i v_i + sum_s (c_is u_n + d_is v_n)
 //   gradT_m = -A_m wx_m - B_m wy_m + sum_s (a_{n,r} wx_n + b_{n,r} wy_n)
 //   divT_m  = (A_m d_m + sum_s c_{n,r} d_n,  B_m d_m + sum_s d_{n,r} d_n)
+// and curl, curlT as div, divT with T_e = m_e x S_e in place of S_e (A', B'
+// the sums of the curl's own-basis terms).
 // where r = rev(m, s) is m's slot in n's list.  The two-ring Laplacian weights
 // W_im (m != i) satisfy lap_i = sum_m W_im (f_m - f_i) = div(grad f)_i.
 void build_op_tables(const HostMesh& m, OpTables& t) {
@@ -439,12 +453,14 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
   t.div.assign(2 * kEll * V, 0.0);
   t.gradT.assign(2 * kEll * V, 0.0);
   t.divT.assign(2 * kEll * V, 0.0);
+  t.curl.assign(2 * kEll * V, 0.0);
+  t.curlT.assign(2 * kEll * V, 0.0);
   for (int64_t i = 0; i < V; ++i) {
     const int64_t s0 = m.csr_off[i];
     const int deg = (int)(m.csr_off[i + 1] - s0);
     const V3 ei = {m.basis[6 * i], m.basis[6 * i + 1], m.basis[6 * i + 2]};
     const V3 ni = {m.basis[6 * i + 3], m.basis[6 * i + 4], m.basis[6 * i + 5]};
-    double A = 0.0, B = 0.0;
+    double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
     for (int s = 0; s < kEll - 1; ++s) t.nbr8[kEll * i + s] = (int32_t)i;
     for (int s = 0; s < deg; ++s) {
       const int32_t nb = m.nbr[s0 + s];
@@ -460,6 +476,12 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
       t.div[2 * (kEll * i + s) + 1] = h * dot(nn, Se);
       A += a;
       B += b;
+      // curl: the face conormal turned about the unit edge midpoint
+      const V3 Te = face_tangent(m, m.eid[s0 + s], Se);
+      t.curl[2 * (kEll * i + s)] = h * dot(en, Te);
+      t.curl[2 * (kEll * i + s) + 1] = h * dot(nn, Te);
+      Ac += h * dot(ei, Te);
+      Bc += h * dot(ni, Te);
     }
     t.nbr8[kEll * i + kEll - 1] = deg | (window_meta(m, i, deg) << 8);
     const int64_t dg = 2 * (kEll * i + kEll - 1);
@@ -467,6 +489,8 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
     t.div[dg] = A; t.div[dg + 1] = B;
     t.gradT[dg] = -A; t.gradT[dg + 1] = -B;
     t.divT[dg] = A; t.divT[dg + 1] = B;
+    t.curl[dg] = Ac; t.curl[dg + 1] = Bc;
+    t.curlT[dg] = Ac; t.curlT[dg + 1] = Bc;
   }
   for (int64_t i = 0; i < V; ++i) {
     const int64_t s0 = m.csr_off[i];
@@ -479,6 +503,8 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
       t.gradT[dst + 1] = t.grad[src + 1];
       t.divT[dst] = t.div[src];
       t.divT[dst + 1] = t.div[src + 1];
+      t.curlT[dst] = t.curl[src];
+      t.curlT[dst + 1] = t.curl[src + 1];
     }
   }
 

@@ -9,12 +9,13 @@ file per device model.
 import json
 import os
 
-from . import BF16, F32, F64, OP_DIVERGENCE, OP_DIVERGENCE_ADJOINT, OP_GRADIENT, OP_GRADIENT_ADJOINT, \
-    OP_LAPLACIAN, set_tune, tune
+from . import BF16, F32, F64, OP_CURL, OP_CURL_ADJOINT, OP_DIVERGENCE, OP_DIVERGENCE_ADJOINT, OP_GRADIENT, \
+    OP_GRADIENT_ADJOINT, OP_LAPLACIAN, set_tune, tune
 
 OPERATORS = {"gradient": (OP_GRADIENT, 1, 2), "divergence": (OP_DIVERGENCE, 2, 1),
              "laplacian": (OP_LAPLACIAN, 1, 1), "gradient_adjoint": (OP_GRADIENT_ADJOINT, 2, 1),
-             "divergence_adjoint": (OP_DIVERGENCE_ADJOINT, 1, 2)}
+             "divergence_adjoint": (OP_DIVERGENCE_ADJOINT, 1, 2), "curl": (OP_CURL, 2, 1),
+             "curl_adjoint": (OP_CURL_ADJOINT, 1, 2)}
 DTYPES = {"float64": F64, "float32": F32, "bfloat16": BF16}
 
 

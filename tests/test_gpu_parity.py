@@ -46,6 +46,8 @@ OPS = {
     "laplacian": (1, pa.laplacian, nabla.laplacian),
     "gradient_adjoint": (2, pa.gradient_adjoint, nabla.gradient_adjoint),
     "divergence_adjoint": (1, pa.divergence_adjoint, nabla.divergence_adjoint),
+    "curl": (2, pa.curl, nabla.curl),
+    "curl_adjoint": (1, pa.curl_adjoint, nabla.curl_adjoint),
 }
 
 
@@ -88,7 +90,8 @@ def test_parity(name, N, L, dtype):
 
 TILE_CODES = {torch.float64: pa.F64, torch.float32: pa.F32}
 OP_BITS = {"gradient": pa.OP_GRADIENT, "divergence": pa.OP_DIVERGENCE, "laplacian": pa.OP_LAPLACIAN,
-           "gradient_adjoint": pa.OP_GRADIENT_ADJOINT, "divergence_adjoint": pa.OP_DIVERGENCE_ADJOINT}
+           "gradient_adjoint": pa.OP_GRADIENT_ADJOINT, "divergence_adjoint": pa.OP_DIVERGENCE_ADJOINT,
+           "curl": pa.OP_CURL, "curl_adjoint": pa.OP_CURL_ADJOINT}
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -201,6 +204,10 @@ def test_dot_product_identities(dtype):
     lhs = (dy * x.double()).sum().item()
     rhs = (y.double() * pa.divergence_adjoint(M, x).double()).sum().item()
     assert abs(lhs - rhs) <= tol * (dy.norm() * x.double().norm()).item()
+    cy = pa.curl(M, y).double()
+    lhs = (cy * x.double()).sum().item()
+    rhs = (y.double() * pa.curl_adjoint(M, x).double()).sum().item()
+    assert abs(lhs - rhs) <= tol * (cy.norm() * x.double().norm()).item()
 
 
 def test_autograd_gradcheck():
@@ -210,6 +217,22 @@ def test_autograd_gradcheck():
     uv = torch.from_numpy(W.normal((M.nnodes, 2, 2), 5)).to(DEV).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda t: pa.div(M, t), (uv,), eps=1e-6, atol=1e-7)
     assert torch.autograd.gradcheck(lambda t: pa.lap(M, t), (f,), eps=1e-6, atol=1e-6)
+    assert torch.autograd.gradcheck(lambda t: pa.rot(M, t), (uv,), eps=1e-6, atol=1e-7)
+
+
+def test_curl_of_solid_body_rotation():
+    """GPU curl of the rotation about the polar axis against 2 sin(lat)/R
+    (FP64; the same bound the oracle meets at O64)."""
+    import math
+    M = gpu_mesh(32)
+    m, g = mesh_and_dual(32)
+    gr = m.grid
+    uv = np.zeros((m.nnodes, 1, 2))
+    uv[:, 0, 0] = gr.coslat            # u = R cos(lat) * (1 / R)
+    z = pa.curl(M, torch.from_numpy(uv).to(DEV)).cpu().numpy()[:, 0]
+    ex = 2.0 * gr.sinlat / R
+    assert math.sqrt(np.sum(g.V * (z - ex) ** 2) / np.sum(g.V * ex ** 2)) < 1e-2
+    np.testing.assert_allclose(z, nabla.curl(m, g, uv)[:, 0], rtol=0, atol=1e-12 * np.abs(ex).max())
 
 
 def test_argument_errors():
@@ -264,7 +287,8 @@ def test_launch_shape_invariance(dtype):
         w = torch.from_numpy(_input(32, L, 2, 22)).to(DEV).to(dtype)
         cases = [(pa.OP_GRADIENT, pa.gradient, x), (pa.OP_DIVERGENCE, pa.divergence, w),
                  (pa.OP_LAPLACIAN, pa.laplacian, x), (pa.OP_GRADIENT_ADJOINT, pa.gradient_adjoint, w),
-                 (pa.OP_DIVERGENCE_ADJOINT, pa.divergence_adjoint, x)]
+                 (pa.OP_DIVERGENCE_ADJOINT, pa.divergence_adjoint, x), (pa.OP_CURL, pa.curl, w),
+                 (pa.OP_CURL_ADJOINT, pa.curl_adjoint, x)]
         for op, fn, inp in cases:
             ref = fn(M, inp)
             for sh in SHAPES:
