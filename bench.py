@@ -148,6 +148,25 @@ def run_gpu(args):
                           "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3)}
             if OP_SWEEPS[op]:
                 per_op[op]["edge_updates_s"] = float(f"{OP_SWEEPS[op] * E * L / (ms * 1e-3):.4g}")
+        # the curl and its adjoint, timed apart from the step (not in value)
+        zt = torch.empty((V, L), dtype=dtype, device=dev)
+        ut = torch.empty((V, L, 2), dtype=dtype, device=dev)
+        extra = {}
+        for name, fn in (("curl", lambda: pa.curl(mesh, g, out=zt)),
+                         ("curl_adjoint", lambda: pa.curl_adjoint(mesh, d, out=ut))):
+            fn()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / args.steps
+            by = 3 * esize * V * L + GEOM_BYTES_PER_NODE * V
+            extra[name] = {"ms": round(ms, 4), "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3),
+                           "edge_updates_s": float(f"{E * L / (ms * 1e-3):.4g}")}
+        del zt, ut
         cs, ca = calls["conservation"]()
         cons = float((cs.abs() / ca).max().item())
         outs = {"gradient": g, "divergence": d, "laplacian": lp, "gradient_adjoint": fT,
@@ -164,7 +183,8 @@ def run_gpu(args):
             per_op[op]["kernel"] = name
         results[dname] = {"ms_per_step": round(t_step * 1e3, 4),
                           "edge_updates_s": float(f"{sweeps * E * L / t_step:.4g}"),
-                          "per_op": per_op, "rel_l2_vs_f64": err, "conservation_max_rel": cons}
+                          "per_op": per_op, "curl_ops": extra, "rel_l2_vs_f64": err,
+                          "conservation_max_rel": cons}
         log(f"{dname}: {t_step * 1e3:.3f} ms/step, " +
             ", ".join(f"{op} {per_op[op]['ms']:.3f}ms {per_op[op]['hbm_frac'] * 100:.0f}%" for op in OPS))
         del f, g, d, lp, fT, gT, outs

@@ -2,7 +2,7 @@
 times, checked against the oracle on sampled outputs and by identities that
 hold at any size.
 
-* O1280 x 137 (FP64, FP32, BF16 storage): every operator at ~700 sampled
+* O1280 x 137 (FP64, FP32, BF16 storage): every operator (and the curl) at ~700 sampled
   nodes (random, polar rows, nodes of degree 5 and 7, row starts, equator).
 * O640 x 137 adjoints (FP64, FP32): autograd backward of sum(w * grad f) and
   of sum(w' * div uv), dot-product tests, central differences on 100 seeded
@@ -76,7 +76,8 @@ def test_o1280_sampled_parity():
            ("divergence", pa.divergence, nabla.divergence_at, "uv"),
            ("laplacian", pa.laplacian, nabla.laplacian_at, "f"),
            ("gradient_adjoint", pa.gradient_adjoint, nabla.gradient_adjoint_at, "uv"),
-           ("divergence_adjoint", pa.divergence_adjoint, nabla.divergence_adjoint_at, "f")]
+           ("divergence_adjoint", pa.divergence_adjoint, nabla.divergence_adjoint_at, "f"),
+           ("curl", pa.curl, nabla.curl_at, "uv")]
     refs = {}
     for name, _, ora, inp in ops:
         src = f64 if inp == "f" else uv64
