@@ -330,11 +330,12 @@ struct WinT {
   }
 };
 
-// Combine deg slot values (slot order) with the node's coefficients and store.
+// Combine deg slot values (slot order) with the node's coefficients: r0 (and
+// r1 for the two-component outputs of OP_GRAD and OP_DIVT).
 template <class S, int OP, int DEG>
-__device__ __forceinline__ void win_emit(S* __restrict__ out, uint32_t o, bool st, int nt,
-                                         const typename WinT<S, OP>::X x0, const typename WinT<S, OP>::X* v,
-                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
+__device__ __forceinline__ void win_combine(const typename WinT<S, OP>::X x0, const typename WinT<S, OP>::X* v,
+                                            const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
+                                            typename Traits<S>::C& r0, typename Traits<S>::C& r1) {
   using C = typename Traits<S>::C;
   if constexpr (OP == OP_GRAD || OP == OP_DIVT) {
     C ax, ay;
@@ -356,10 +357,8 @@ __device__ __forceinline__ void win_emit(S* __restrict__ out, uint32_t o, bool s
         ay = fma(cf[s].y, v[s], ay);
       }
     }
-    if (st) {
-      if (nt) st2<true>(out + 2 * (size_t)o, ax, ay);
-      else st2<false>(out + 2 * (size_t)o, ax, ay);
-    }
+    r0 = ax;
+    r1 = ay;
   } else {
     C acc = dg.x * x0.x;
     acc = fma(dg.y, x0.y, acc);
@@ -368,11 +367,33 @@ __device__ __forceinline__ void win_emit(S* __restrict__ out, uint32_t o, bool s
       acc = fma(cf[s].x, v[s].x, acc);
       acc = fma(cf[s].y, v[s].y, acc);
     }
-    if (st) {
-      if (nt) st1<true>(out + (size_t)o, acc);
-      else st1<false>(out + (size_t)o, acc);
-    }
+    r0 = acc;
+    r1 = 0;
   }
+}
+
+// Store of a combined value at node-level index o (two components for
+// OP_GRAD and OP_DIVT).
+template <class S, int OP>
+__device__ __forceinline__ void win_store(S* __restrict__ out, uint32_t o, int nt, typename Traits<S>::C r0,
+                                          typename Traits<S>::C r1) {
+  if constexpr (OP == OP_GRAD || OP == OP_DIVT) {
+    if (nt) st2<true>(out + 2 * (size_t)o, r0, r1);
+    else st2<false>(out + 2 * (size_t)o, r0, r1);
+  } else {
+    if (nt) st1<true>(out + (size_t)o, r0);
+    else st1<false>(out + (size_t)o, r0);
+  }
+}
+
+// Combine and store (lanes with st set).
+template <class S, int OP, int DEG>
+__device__ __forceinline__ void win_emit(S* __restrict__ out, uint32_t o, bool st, int nt,
+                                         const typename WinT<S, OP>::X x0, const typename WinT<S, OP>::X* v,
+                                         const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg) {
+  typename Traits<S>::C r0, r1;
+  win_combine<S, OP, DEG>(x0, v, cf, dg, r0, r1);
+  if (st) win_store<S, OP>(out, o, nt, r0, r1);
 }
 
 // Run-time choice among register values, written as element-wise selects so
@@ -776,63 +797,105 @@ __device__ __forceinline__ void tile_positions(const char* lds, uint32_t off, ui
   cnt = (int)(last >> kLocCountShift);
 }
 
+// Marks a value as computed here: the compiler may not sink its computation
+// (and the LDS reads feeding it) into the predicated store that follows, so
+// the reads of all slices of a step issue together.
+template <class T>
+__device__ __forceinline__ void keep(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
 // One node of a 1-ring operator: DEG slots, U slices of 64 levels per step.
+// Each lane's LDS address of a slot is formed once per node; the level slices
+// of a step then sit at constant offsets from it.  Lanes past the chunk's
+// last level read (and drop) values beyond their column, which stay inside
+// the tile buffer's tail of 64 U levels (tile_tail_bytes).
 template <class S, int OP, int U, int DEG>
 __device__ __forceinline__ void tile_node1(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
                                            const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
                                            uint32_t obase, int klc, int lane) {
   using X = typename WinT<S, OP>::X;
-  constexpr uint32_t kEl = (uint32_t)sizeof(S) * TileRec<S, OP>::kCin;   // bytes per level in LDS
-  S* __restrict__ out = static_cast<S*>(a.out);
-  for (int kb = 0; kb < klc; kb += 64 * U) {
+  using C = typename Traits<S>::C;
+  using R = TileRec<S, OP>;
+  constexpr uint32_t kEl = (uint32_t)sizeof(S) * R::kCin;   // bytes per level in LDS
+  constexpr uint32_t kOut = (OP == OP_GRAD || OP == OP_DIVT) ? 2 : 1;
+  // BF16: values are left to the compiler's placement, which keeps the
+  // vector-input kernels within 64 VGPRs (four workgroups per CU)
+  constexpr bool kKeep = sizeof(S) != 2;
+  const uint32_t lo = (uint32_t)lane * kEl;
+  uint32_t vb[DEG];
+#pragma unroll
+  for (int s = 0; s < DEG; ++s) vb[s] = so[s] + lo;
+  const uint32_t vx = xo + lo;
+  S* __restrict__ out = static_cast<S*>(a.out) + (size_t)kOut * (obase + (uint32_t)lane);
+  auto step = [&](int kb) {
+    const uint32_t ko = (uint32_t)kb * kEl;
     X v[U][DEG], x0[U];
-    bool st[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = kb + 64 * u + lane;
-      st[u] = k < klc;
-      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * kEl;
 #pragma unroll
-      for (int s = 0; s < DEG; ++s) v[u][s] = lds_elem<S, X>(lds, so[s] + kk);
-      x0[u] = lds_elem<S, X>(lds, xo + kk);
+      for (int s = 0; s < DEG; ++s) v[u][s] = lds_elem<S, X>(lds, vb[s] + ko + 64u * kEl * u);
+      x0[u] = lds_elem<S, X>(lds, vx + ko + 64u * kEl * u);
+    }
+    C r0[U], r1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      win_combine<S, OP, DEG>(x0[u], v[u], cf, dg, r0[u], r1[u]);
+      if constexpr (kKeep) {
+        keep(r0[u]);
+        if constexpr (kOut == 2) keep(r1[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      win_emit<S, OP, DEG>(out, obase + (uint32_t)(kb + 64 * u + lane), st[u], a.nt, x0[u], v[u], cf, dg);
-  }
+      if (kb + 64 * u + lane < klc) win_store<S, OP>(out + (size_t)kOut * kb, 64u * u, a.nt, r0[u], r1[u]);
+  };
+  step(0);
+  for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
 }
 
 // One node of the two-ring Laplacian: NS entries (padded with the node itself
-// and zero weights, which add exact zeros), sum_m W_im (f_m - f_i).
+// and zero weights, which add exact zeros), sum_m W_im (f_m - f_i).  Addresses
+// as in tile_node1.
 template <class S, int U, int NS>
 __device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
                                            const typename Traits<S>::C* w, uint32_t obase, int klc, int lane) {
   using C = typename Traits<S>::C;
-  S* __restrict__ out = static_cast<S*>(a.out);
-  for (int kb = 0; kb < klc; kb += 64 * U) {
+  constexpr uint32_t kEl = (uint32_t)sizeof(S);
+  const uint32_t lo = (uint32_t)lane * kEl;
+  uint32_t vb[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) vb[s] = so[s] + lo;
+  const uint32_t vx = xo + lo;
+  S* __restrict__ out = static_cast<S*>(a.out) + (size_t)(obase + (uint32_t)lane);
+  auto step = [&](int kb) {
+    const uint32_t ko = (uint32_t)kb * kEl;
     C v[U][NS], x0[U];
-    bool st[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = kb + 64 * u + lane;
-      st[u] = k < klc;
-      const uint32_t kk = (uint32_t)(k < klc ? k : klc - 1) * (uint32_t)sizeof(S);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) v[u][s] = lds_elem<S, C>(lds, so[s] + kk);
-      x0[u] = lds_elem<S, C>(lds, xo + kk);
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_elem<S, C>(lds, vb[s] + ko + 64u * kEl * u);
+      x0[u] = lds_elem<S, C>(lds, vx + ko + 64u * kEl * u);
+    }
+    C acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[u] = fma(w[s], v[u][s] - x0[u], acc[u]);
+      keep(acc[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      C acc = 0;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc = fma(w[s], v[u][s] - x0[u], acc);
-      if (st[u]) {
-        const uint32_t o = obase + (uint32_t)(kb + 64 * u + lane);
-        if (a.nt) st1<true>(out + (size_t)o, acc);
-        else st1<false>(out + (size_t)o, acc);
+      if (kb + 64 * u + lane < klc) {
+        S* o = out + (size_t)(kb + 64 * u);
+        if (a.nt) st1<true>(o, acc[u]);
+        else st1<false>(o, acc[u]);
       }
     }
-  }
+  };
+  step(0);
+  for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
 }
 
 // Copy of one tile (chunk) into an LDS buffer by W waves: the records as one
@@ -1551,6 +1614,14 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   g.ring = op == OP_LAP ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
+  // one tile per workgroup: the read-past tail behind the largest tile must
+  // not cost a workgroup per CU -- with n = LDS / budget workgroups per CU,
+  // the budget leaves LDS / n - budget >= the largest tail (3 x 64 levels)
+  if (sh.lds_tiles == 3) {
+    const int64_t n = (int64_t)kLdsPerCu / g.budget > 1 ? (int64_t)kLdsPerCu / g.budget : 1;
+    const int64_t cap = (int64_t)kLdsPerCu / n - 3 * 64 * cin * es;
+    if (g.budget > cap) g.budget = cap;
+  }
   if (dtype == DT_BF16) {
     // whole columns only; per column the data, its offset-table entry and up
     // to 8 bytes of alignment padding, plus 16 bytes of table alignment
@@ -1596,6 +1667,17 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   return g;
 }
 
+int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U) {
+  const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
+  // a step reads 64 U levels (64 on the single-slice paths) from level 0 on:
+  // past a chunk of k levels up to round_up(k, 64 U) - k levels
+  const int64_t step = 64 * (int64_t)U;
+  const int64_t last = nlev - (int64_t)((nlev - 1) / KL) * KL;
+  const int64_t t0 = (KL + step - 1) / step * step - KL, t1 = (last + step - 1) / step * step - last;
+  return (t0 > t1 ? t0 : t1) * cin * es;
+}
+
 int64_t tile_record_bytes(int op, int dtype) {
   switch (op * 2 + (dtype == DT_F64 ? 1 : 0)) {
     case OP_LAP * 2: return TileRec<float, OP_LAP>::kBytes;
@@ -1629,7 +1711,16 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
   const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
-  const uint32_t lds_need = dt.lds_bytes + (bf ? 16u : 0u);
+  const int U3 = [&] {
+    const int nsl = (dt.KL + 63) / 64;
+    const int u = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
+    return u < nsl ? u : nsl;
+  }();
+  // one tile per workgroup: lanes past a column's last level read into a
+  // tail behind the buffer
+  const uint32_t lds_need =
+      dt.lds_bytes + (bf ? 16u : 0u) +
+      (shape.lds_tiles == 3 && dt.KL >= 1 ? (uint32_t)tile_tail_bytes(op, dtype, dt.KL, nlev, U3) : 0u);
   if (dt.KL < 1 || dt.KL > nlev || dt.nchunks != (nlev + dt.KL - 1) / dt.KL || lds_need > kLdsPerCu ||
       dt.col_bytes != colb || dt.row_bytes != row || (bf && (dt.KL != nlev || shape.lds_tiles != 3)))
     return hipErrorInvalidValue;
@@ -1645,9 +1736,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   a.nchunks = dt.nchunks;
   a.nt = nt_of(shape) ? 1 : 0;
   if (shape.lds_tiles == 3) {
-    const int nsl = (dt.KL + 63) / 64;
-    int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
-    if (U > nsl) U = nsl;
+    const int U = U3;
     switch (dtype) {
       case DT_F64: return launch_tiles_t<double>(kernel_op(op), a, U, lds_need, shape, stream);
       case DT_F32: return launch_tiles_t<float>(kernel_op(op), a, U, lds_need, shape, stream);

@@ -104,6 +104,11 @@ void kernel_label(int op, int dtype, int nlev, const Shape& resolved, char* buf,
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh);
 // Bytes of one node record of the tile path (LDS bytes per tile node).
 int64_t tile_record_bytes(int op, int dtype);
+// LDS bytes kept free behind a one-tile-per-workgroup buffer: lanes past a
+// column's last level read (and drop) values beyond it, up to the next
+// multiple of 64 U levels of a chunk (chunks of KL levels, the last one
+// shorter; U slices per step).
+int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U);
 // Packs a tiling's node records for (op, dtype) into rec ([V] records in tile
 // order: coefficients, LDS positions, node index).
 hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,
