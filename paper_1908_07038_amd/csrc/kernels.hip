@@ -968,12 +968,145 @@ __device__ __forceinline__ void tile_offsets(const char* lds, uint32_t tab, uint
   }
 }
 
+// One node of a tile (record tn) by one wave, 64 lanes over the levels of
+// the chunk: positions and coefficients from the record, then the stencil.
+template <class S, int OP, int U>
+__device__ __forceinline__ void tile_eval(const TileArgs& a, const char* lds, int32_t tn, uint32_t data_off,
+                                          uint32_t colB, int k0, int klc, int lane) {
+  using R = TileRec<S, OP>;
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  const uint32_t ro = (uint32_t)tn * R::kBytes;
+  const uint32_t obase = uni((uint32_t)lds_ld<int32_t>(lds, ro + R::kIdOff)) * (uint32_t)a.L + (uint32_t)k0;
+  uint32_t pos[R::kEntries - 1], self;
+  int ne;
+  tile_positions<R::kEntries>(lds, ro + R::kCoefB, pos, self, ne);
+  uint32_t so[R::kEntries - 1], xo;
+  if constexpr (R::kRing2) {
+    C w[R::kEntries - 1];
+#pragma unroll
+    for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C));
+    if (ne <= 18) {
+      tile_offsets<S, 18>(lds, data_off, data_off, colB, pos, self, so, xo);
+      tile_node2<S, U, 18>(a, lds, so, xo, w, obase, klc, lane);
+    } else {
+      tile_offsets<S, R::kEntries - 1>(lds, data_off, data_off, colB, pos, self, so, xo);
+      tile_node2<S, 1, R::kEntries - 1>(a, lds, so, xo, w, obase, klc, lane);
+    }
+  } else {
+    C2 cf[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
+    const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
+    tile_offsets<S, 7>(lds, data_off, data_off, colB, pos, self, so, xo);
+    switch (ne) {
+      case 6: tile_node1<S, OP, U, 6>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+      case 5: tile_node1<S, OP, 1, 5>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+      case 7: tile_node1<S, OP, 1, 7>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+      case 4: tile_node1<S, OP, 1, 4>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+      default: tile_node1<S, OP, 1, 3>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
+    }
+  }
+}
+
+// Tail levels [kt, kt + rem) of all nodes of a tile, rem <= 32: G = 64 / rem
+// nodes share a wave, lane = (node j, level t), each lane with its node's
+// record (reads within a node group are broadcasts).  The same slot-order
+// arithmetic as tile_eval; 1-ring nodes of another degree than 6 in a group
+// take the padded seventh slot under a select, so every lane combines
+// exactly its own stencil.
+template <class S, int OP>
+__device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, int32_t nnodes, uint32_t data_off,
+                                          uint32_t colB, int k0, int kt, int rem, int wave, int W, int lane) {
+  using R = TileRec<S, OP>;
+  using C = typename Traits<S>::C;
+  using C2 = typename Traits<S>::C2;
+  using X = typename WinT<S, OP>::X;
+  constexpr uint32_t kEl = (uint32_t)sizeof(S) * R::kCin;
+  constexpr int NE = R::kEntries - 1;
+  const int G = 64 / rem;
+  const int j = lane / rem, t = lane - j * rem;
+  S* __restrict__ out = static_cast<S*>(a.out);
+  for (int32_t g0 = wave * G; g0 < nnodes; g0 += W * G) {
+    const int32_t tn = g0 + j;
+    const bool ok = j < G && tn < nnodes;
+    const uint32_t ro = (uint32_t)(ok ? tn : g0) * R::kBytes;
+    uint32_t w32[R::kEntries / 2];
+#pragma unroll
+    for (int q = 0; q < R::kEntries / 8; ++q) {
+      const uint4 r = lds_ld<uint4>(lds, ro + R::kCoefB + 16 * q);
+      w32[4 * q] = r.x;
+      w32[4 * q + 1] = r.y;
+      w32[4 * q + 2] = r.z;
+      w32[4 * q + 3] = r.w;
+    }
+    const uint32_t lev = (uint32_t)(kt + t) * kEl;
+    auto off = [&](uint32_t pos) -> uint32_t {
+      if constexpr (sizeof(S) == 2) return lds_ld<uint32_t>(lds, data_off + 4 * pos) + lev;   // BF16 table
+      else return data_off + pos * colB + lev;
+    };
+    const uint32_t last = w32[R::kEntries / 2 - 1] >> 16;
+    const X x0 = lds_elem<S, X>(lds, off(last & ((1u << kLocCountShift) - 1)));
+    const int ne = (int)(last >> kLocCountShift);
+    const uint32_t o = (uint32_t)lds_ld<int32_t>(lds, ro + R::kIdOff) * (uint32_t)a.L + (uint32_t)(k0 + kt + t);
+    if constexpr (R::kRing2) {
+      auto run = [&](auto ns) {
+        constexpr int NS = decltype(ns)::value;
+        C acc = 0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const uint32_t pos = (q & 1) ? (w32[q >> 1] >> 16) : (w32[q >> 1] & 0xffffu);
+          const C v = lds_elem<S, C>(lds, off(pos));
+          acc = fma(lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C)), v - x0, acc);
+        }
+        if (ok) {
+          if (a.nt) st1<true>(out + (size_t)o, acc);
+          else st1<false>(out + (size_t)o, acc);
+        }
+      };
+      if (__all(!ok || ne <= 18)) run(std::integral_constant<int, 18>());
+      else run(std::integral_constant<int, NE>());
+    } else {
+      C2 cf[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
+      const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
+      X v[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        const uint32_t pos = (q & 1) ? (w32[q >> 1] >> 16) : (w32[q >> 1] & 0xffffu);
+        v[q] = lds_elem<S, X>(lds, off(pos));
+      }
+      C r0, r1;
+      if (__all(!ok || ne == 6)) {
+        win_combine<S, OP, 6>(x0, v, cf, dg, r0, r1);
+      } else {
+        // per-lane degree: slots past ne leave the sums unchanged
+        C a0, a1, b0, b1;
+        win_combine<S, OP, 3>(x0, v, cf, dg, b0, b1);
+#pragma unroll
+        for (int d = 4; d <= 7; ++d) {
+          if (d == 4) win_combine<S, OP, 4>(x0, v, cf, dg, a0, a1);
+          if (d == 5) win_combine<S, OP, 5>(x0, v, cf, dg, a0, a1);
+          if (d == 6) win_combine<S, OP, 6>(x0, v, cf, dg, a0, a1);
+          if (d == 7) win_combine<S, OP, 7>(x0, v, cf, dg, a0, a1);
+          if (ne >= d) {
+            b0 = a0;
+            b1 = a1;
+          }
+        }
+        r0 = b0;
+        r1 = b1;
+      }
+      if (ok) win_store<S, OP>(out, o, a.nt, r0, r1);
+    }
+  }
+}
+
 template <class S, int OP, int U>
 __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int remap) {
   extern __shared__ __align__(16) char lds[];
   using R = TileRec<S, OP>;
-  using C = typename Traits<S>::C;
-  using C2 = typename Traits<S>::C2;
   const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
   if (lb >= nblocks) return;
   const int64_t tile = lb / a.nchunks;
@@ -989,40 +1122,15 @@ __global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int r
   const uint32_t data_off = (uint32_t)nnodes * R::kBytes;   // BF16: the offset table starts here
   __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
   __syncthreads();
-  // compute: node tn of the tile goes to wave tn mod W
-  for (int32_t tn = wave; tn < nnodes; tn += W) {
-    const uint32_t ro = (uint32_t)tn * R::kBytes;
-    const uint32_t obase = uni((uint32_t)lds_ld<int32_t>(lds, ro + R::kIdOff)) * (uint32_t)a.L + (uint32_t)k0;
-    uint32_t pos[R::kEntries - 1], self;
-    int ne;
-    tile_positions<R::kEntries>(lds, ro + R::kCoefB, pos, self, ne);
-    uint32_t so[R::kEntries - 1], xo;
-    if constexpr (R::kRing2) {
-      C w[R::kEntries - 1];
-#pragma unroll
-      for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C));
-      if (ne <= 18) {
-        tile_offsets<S, 18>(lds, data_off, data_off, colB, pos, self, so, xo);
-        tile_node2<S, U, 18>(a, lds, so, xo, w, obase, klc, lane);
-      } else {
-        tile_offsets<S, R::kEntries - 1>(lds, data_off, data_off, colB, pos, self, so, xo);
-        tile_node2<S, 1, R::kEntries - 1>(a, lds, so, xo, w, obase, klc, lane);
-      }
-    } else {
-      C2 cf[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
-      const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
-      tile_offsets<S, 7>(lds, data_off, data_off, colB, pos, self, so, xo);
-      switch (ne) {
-        case 6: tile_node1<S, OP, U, 6>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
-        case 5: tile_node1<S, OP, 1, 5>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
-        case 7: tile_node1<S, OP, 1, 7>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
-        case 4: tile_node1<S, OP, 1, 4>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
-        default: tile_node1<S, OP, 1, 3>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
-      }
-    }
-  }
+  // compute: node tn of the tile goes to wave tn mod W for whole 64-level
+  // slices; a short remainder (1..32 levels) of all nodes is packed G = 64 /
+  // rem nodes to a wave
+  const int rem = klc & 63;
+  const bool pack = rem != 0 && rem <= 32;
+  const int kmain = pack ? klc - rem : klc;
+  if (kmain > 0)
+    for (int32_t tn = wave; tn < nnodes; tn += W) tile_eval<S, OP, U>(a, lds, tn, data_off, colB, k0, kmain, lane);
+  if (pack) tile_tail<S, OP>(a, lds, nnodes, data_off, colB, k0, kmain, rem, wave, W, lane);
 }
 
 // Packs the node records of a tiling in tile order: record q is node
@@ -1131,6 +1239,10 @@ __device__ __forceinline__ void tile_consume(const TileArgs& a, int64_t lb, cons
   const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
   const uint32_t colB = (uint32_t)klc * R::kCin * (uint32_t)sizeof(S);   // LDS column stride (this chunk)
   const uint32_t data_off = (uint32_t)nnodes * R::kBytes;
+  if (P == 64) {   // one node per wave, as in the one-tile form
+    for (int32_t tn = cw; tn < nnodes; tn += NC) tile_eval<S, OP, U>(a, buf, tn, data_off, colB, k0, klc, lane);
+    return;
+  }
   const int G = 64 / P;
   const int j = lane / P, t = lane - (lane / P) * P;
   for (int32_t tn0 = cw * G; tn0 < nnodes; tn0 += NC * G) {
@@ -1459,9 +1571,8 @@ hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds,
 }
 
 template <class S, int OP>
-hipError_t launch_tile2_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t buf_bytes, int64_t nblocks, int remap,
-                          int nprod, int P, hipStream_t st) {
-  const uint32_t lds = 2 * buf_bytes;
+hipError_t launch_tile2_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t buf_bytes, uint32_t lds,
+                          int64_t nblocks, int remap, int nprod, int P, hipStream_t st) {
   const void* fn = U == 1 ? reinterpret_cast<const void*>(&k_tile2<S, OP, 1>)
                    : U == 2 ? reinterpret_cast<const void*>(&k_tile2<S, OP, 2>)
                             : reinterpret_cast<const void*>(&k_tile2<S, OP, 3>);
@@ -1478,19 +1589,19 @@ hipError_t launch_tile2_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t buf
 }
 
 template <class S>
-hipError_t launch_tiles2_t(int op, const TileArgs& a, int U, uint32_t buf_bytes, int nprod, int ncons, int per_cu,
-                           int num_cus, int P, const Shape& sh, hipStream_t st) {
+hipError_t launch_tiles2_t(int op, const TileArgs& a, int U, uint32_t buf_bytes, uint32_t lds, int nprod, int ncons,
+                           int per_cu, int num_cus, int P, const Shape& sh, hipStream_t st) {
   const int64_t nblocks = a.ntiles * a.nchunks;
   int64_t grid = (int64_t)per_cu * num_cus;
   if (grid > nblocks) grid = nblocks;
   const int remap = (sh.xcd_remap && grid % 8 == 0) ? 1 : 0;
   const dim3 g((unsigned)grid), b((unsigned)(64 * (nprod + ncons)));
   switch (op) {
-    case OP_GRAD: return launch_tile2_u<S, OP_GRAD>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
-    case OP_DIV: return launch_tile2_u<S, OP_DIV>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
-    case OP_GRADT: return launch_tile2_u<S, OP_GRADT>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
-    case OP_DIVT: return launch_tile2_u<S, OP_DIVT>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
-    case OP_LAP: return launch_tile2_u<S, OP_LAP>(a, U, g, b, buf_bytes, nblocks, remap, nprod, P, st);
+    case OP_GRAD: return launch_tile2_u<S, OP_GRAD>(a, U, g, b, buf_bytes, lds, nblocks, remap, nprod, P, st);
+    case OP_DIV: return launch_tile2_u<S, OP_DIV>(a, U, g, b, buf_bytes, lds, nblocks, remap, nprod, P, st);
+    case OP_GRADT: return launch_tile2_u<S, OP_GRADT>(a, U, g, b, buf_bytes, lds, nblocks, remap, nprod, P, st);
+    case OP_DIVT: return launch_tile2_u<S, OP_DIVT>(a, U, g, b, buf_bytes, lds, nblocks, remap, nprod, P, st);
+    case OP_LAP: return launch_tile2_u<S, OP_LAP>(a, U, g, b, buf_bytes, lds, nblocks, remap, nprod, P, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1586,9 +1697,9 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   if (dtype == DT_F32)
     d = op == OP_LAP ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else if (dtype == DT_BF16)
-    d = op == OP_LAP ? Def{3, 32, 4, 0, 0, 0, 4} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+    d = op == OP_LAP ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else
-    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 160, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
+    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;
@@ -1614,12 +1725,14 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   g.ring = op == OP_LAP ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
-  // one tile per workgroup: the read-past tail behind the largest tile must
-  // not cost a workgroup per CU -- with n = LDS / budget workgroups per CU,
-  // the budget leaves LDS / n - budget >= the largest tail (3 x 64 levels)
-  if (sh.lds_tiles == 3) {
-    const int64_t n = (int64_t)kLdsPerCu / g.budget > 1 ? (int64_t)kLdsPerCu / g.budget : 1;
-    const int64_t cap = (int64_t)kLdsPerCu / n - 3 * 64 * cin * es;
+  // the read-past tail behind a workgroup's buffers (one, or two for the
+  // persistent form) must not cost a workgroup per CU: with n = LDS / (nb
+  // budget) workgroups per CU, the budget leaves room for the largest tail
+  // (3 x 64 levels)
+  if (sh.lds_tiles == 3 || sh.lds_tiles == 1) {
+    const int64_t nb = sh.lds_tiles == 1 ? 2 : 1;
+    const int64_t n = (int64_t)kLdsPerCu / (nb * g.budget) > 1 ? (int64_t)kLdsPerCu / (nb * g.budget) : 1;
+    const int64_t cap = (((int64_t)kLdsPerCu / n - 3 * 64 * cin * es) / nb) & ~(int64_t)15;
     if (g.budget > cap) g.budget = cap;
   }
   if (dtype == DT_BF16) {
@@ -1667,6 +1780,16 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   return g;
 }
 
+int tile_slices(int KL, const Shape& sh) {
+  // whole 64-level slices of a chunk: a remainder of 1..32 levels goes to the
+  // packed tail pass
+  const int rem = KL & 63;
+  const int kmain = rem != 0 && rem <= 32 ? KL - rem : KL;
+  const int nsl = (kmain + 63) / 64 > 0 ? (kmain + 63) / 64 : 1;
+  const int u = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
+  return u < nsl ? u : nsl;
+}
+
 int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U) {
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
   const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
@@ -1711,11 +1834,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
   const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
-  const int U3 = [&] {
-    const int nsl = (dt.KL + 63) / 64;
-    const int u = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
-    return u < nsl ? u : nsl;
-  }();
+  const int U3 = tile_slices(dt.KL, shape);
   // one tile per workgroup: lanes past a column's last level read into a
   // tail behind the buffer
   const uint32_t lds_need =
@@ -1749,19 +1868,23 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   const int ncons = shape.tile_waves > 0 ? shape.tile_waves : 6;
   if (nprod + ncons > (dtype == DT_F64 ? 8 : 16) || (nprod & (nprod - 1))) return hipErrorInvalidValue;
   const uint32_t buf_bytes = (dt.lds_bytes + 15u) & ~15u;
-  // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
-  int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;
-  while (per_cu > 1 && (uint64_t)2 * buf_bytes * per_cu > kLdsPerCu) --per_cu;
-  if ((uint64_t)2 * buf_bytes > kLdsPerCu) return hipErrorInvalidValue;
   const int P = lanes_per_node(dt.KL, shape);
   const int nsl = (dt.KL + P - 1) / P;
   int U = shape.slices_per_iter > 0 ? shape.slices_per_iter : 3;
   if (U > nsl) U = nsl;
+  // whole-wave nodes read past a column's last level, as in the one-tile form
+  const uint32_t lds = 2 * buf_bytes + (P == 64 ? (uint32_t)tile_tail_bytes(op, dtype, dt.KL, nlev, U) : 0u);
+  // workgroups per CU as asked, as far as their two buffers fit the CU's LDS
+  int per_cu = shape.tile_wgs_per_cu > 0 ? shape.tile_wgs_per_cu : 1;
+  while (per_cu > 1 && (uint64_t)lds * per_cu > kLdsPerCu) --per_cu;
+  if (lds > kLdsPerCu) return hipErrorInvalidValue;
   switch (dtype) {
     case DT_F64:
-      return launch_tiles2_t<double>(kernel_op(op), a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
+      return launch_tiles2_t<double>(kernel_op(op), a, U, buf_bytes, lds, nprod, ncons, per_cu, num_cus, P, shape,
+                                     stream);
     case DT_F32:
-      return launch_tiles2_t<float>(kernel_op(op), a, U, buf_bytes, nprod, ncons, per_cu, num_cus, P, shape, stream);
+      return launch_tiles2_t<float>(kernel_op(op), a, U, buf_bytes, lds, nprod, ncons, per_cu, num_cus, P, shape,
+                                    stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1773,10 +1896,14 @@ void kernel_label(int op, int dtype, int nlev, const Shape& sh, char* buf, int l
   if (uses_tiles(op, dtype, nlev, sh)) {
     const TileGeom g = tile_geom(op, dtype, nlev, sh);
     if (g.KL > 0) {
-      const int P = sh.lds_tiles == 3 ? 64 : lanes_per_node(g.KL, sh);
-      const int nsl = (g.KL + P - 1) / P;
-      U = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
-      if (U > nsl) U = nsl;
+      if (sh.lds_tiles == 3) {
+        U = tile_slices(g.KL, sh);
+      } else {
+        const int P = lanes_per_node(g.KL, sh);
+        const int nsl = (g.KL + P - 1) / P;
+        U = sh.slices_per_iter > 0 ? sh.slices_per_iter : 3;
+        if (U > nsl) U = nsl;
+      }
       name = sh.lds_tiles == 3 ? "k_tile" : "k_tile2";
     }
   }

@@ -109,6 +109,10 @@ int64_t tile_record_bytes(int op, int dtype);
 // multiple of 64 U levels of a chunk (chunks of KL levels, the last one
 // shorter; U slices per step).
 int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U);
+// Level slices per step of the one-tile form for chunks of KL levels: the
+// whole 64-level slices (a remainder of 1..32 levels is evaluated in a packed
+// pass, several nodes to a wave), at most 3 or slices_per_iter.
+int tile_slices(int KL, const Shape& sh);
 // Packs a tiling's node records for (op, dtype) into rec ([V] records in tile
 // order: coefficients, LDS positions, node index).
 hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,

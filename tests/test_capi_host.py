@@ -116,15 +116,20 @@ def test_describe_resolves_the_default_paths():
     paths for FP32/FP64 columns of more than 32 levels, the row-window walk
     or the gather otherwise, and an explicit shape overriding the default."""
     M = pa.Mesh("O8", device=-1)
-    cases = [(pa.OP_GRADIENT, pa.F32, 137, "k_tile<float, 0, 3>"),
-             (pa.OP_DIVERGENCE_ADJOINT, pa.F32, 137, "k_tile<float, 3, 3>"),
-             (pa.OP_DIVERGENCE, pa.F32, 137, "k_tile<float, 1, 3>"),
-             (pa.OP_LAPLACIAN, pa.F32, 137, "k_tile<float, 4, 3>"),
-             (pa.OP_GRADIENT, pa.F64, 137, "k_tile<double, 0, 3>"),
-             (pa.OP_DIVERGENCE, pa.F64, 137, "k_tile<double, 1, 3>"),
-             (pa.OP_LAPLACIAN, pa.F64, 137, "k_tile<double, 4, 3>"),
-             (pa.OP_GRADIENT, pa.BF16, 137, "k_tile<unsigned short, 0, 3>"),
-             (pa.OP_LAPLACIAN, pa.BF16, 137, "k_tile<unsigned short, 4, 3>"),
+    # 137 levels: two whole 64-level slices per step, the 9-level remainder
+    # in the packed tail pass; 160 levels: three slices (remainder of 32)
+    cases = [(pa.OP_GRADIENT, pa.F32, 137, "k_tile<float, 0, 2>"),
+             (pa.OP_DIVERGENCE_ADJOINT, pa.F32, 137, "k_tile<float, 3, 2>"),
+             (pa.OP_DIVERGENCE, pa.F32, 137, "k_tile<float, 1, 2>"),
+             (pa.OP_LAPLACIAN, pa.F32, 137, "k_tile<float, 4, 2>"),
+             (pa.OP_LAPLACIAN, pa.F32, 160, "k_tile<float, 4, 2>"),
+             (pa.OP_LAPLACIAN, pa.F32, 170, "k_tile<float, 4, 3>"),
+             (pa.OP_GRADIENT, pa.F64, 137, "k_tile<double, 0, 2>"),
+             # two level chunks of 69 and 68 levels: one whole slice each
+             (pa.OP_DIVERGENCE, pa.F64, 137, "k_tile<double, 1, 1>"),
+             (pa.OP_LAPLACIAN, pa.F64, 137, "k_tile<double, 4, 2>"),
+             (pa.OP_GRADIENT, pa.BF16, 137, "k_tile<unsigned short, 0, 2>"),
+             (pa.OP_LAPLACIAN, pa.BF16, 137, "k_tile<unsigned short, 4, 2>"),
              (pa.OP_GRADIENT, pa.F32, 19, "k_op<float, 0, 1>")]
     for op, dt, L, name in cases:
         shape, kernel = pa.describe(M, op, dt, L)

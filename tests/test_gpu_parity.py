@@ -96,12 +96,17 @@ OP_BITS = {"gradient": pa.OP_GRADIENT, "divergence": pa.OP_DIVERGENCE, "laplacia
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("name", list(OPS))
-@pytest.mark.parametrize("N,L,kb", [(32, 137, 0), (32, 33, 8), (2, 70, 64), (32, 200, 16)])
-def test_parity_lds_tiles(name, N, L, kb, dtype):
-    """The LDS tile path against the oracle (whole columns and level chunks)."""
-    print(f"case tiles {name} O{N} x {L} kb {kb} {dtype}", flush=True)
+@pytest.mark.parametrize("form", [1, 3], ids=["persistent", "one_tile"])
+@pytest.mark.parametrize("N,L,kb", [(32, 137, 0), (32, 33, 8), (2, 70, 64), (32, 200, 16), (8, 96, 0),
+                                    (8, 65, 0), (8, 40, 0)])
+def test_parity_lds_tiles(name, N, L, kb, form, dtype):
+    """The LDS tile paths against the oracle: whole columns and level chunks,
+    remainders past the whole 64-level slices of 1 (65), 6 (70), 8 (200), 9
+    (137) and 32 (96) levels, which the one-tile form evaluates in its packed
+    tail pass, and columns of 33 and 40 levels (one partial slice)."""
+    print(f"case tiles {name} O{N} x {L} kb {kb} form {form} {dtype}", flush=True)
     M = gpu_mesh(N)
-    pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], dict(lds_tiles=1, tile_kb=kb))
+    pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], dict(lds_tiles=form, tile_kb=kb))
     try:
         y, ref, _, _, _ = _run(name, N, L, dtype)
     finally:
@@ -282,7 +287,7 @@ def test_launch_shape_invariance(dtype):
     zero) as the default one: the per-element slot order never changes."""
     M = gpu_mesh(32)
     codes = {torch.float64: pa.F64, torch.float32: pa.F32, torch.bfloat16: pa.BF16}
-    for L in (137, 91, 40, 19):
+    for L in (137, 96, 91, 65, 40, 19):
         x = torch.from_numpy(_input(32, L, 1, 21)).to(DEV).to(dtype)
         w = torch.from_numpy(_input(32, L, 2, 22)).to(DEV).to(dtype)
         cases = [(pa.OP_GRADIENT, pa.gradient, x), (pa.OP_DIVERGENCE, pa.divergence, w),
