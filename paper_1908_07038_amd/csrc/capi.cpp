@@ -261,7 +261,8 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   if (!t) return ATLAS_OK;
   if (t->waves_per_block) {
     const int w = t->waves_per_block;
-    if (w != 1 && w != 2 && w != 4 && w != 8) return fail(ATLAS_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
+    if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16)
+      return fail(ATLAS_EINVAL, "waves_per_block must be 1, 2, 4, 8 or 16");
     s.waves_per_block = w;
   }
   if (t->nodes_per_wave) {

@@ -1103,8 +1103,13 @@ __device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, in
   }
 }
 
+// Up to 16 waves per workgroup (at most 128 registers per lane), 8 for the
+// three-slice FP64 Laplacian, which needs more registers.
 template <class S, int OP, int U>
-__global__ __launch_bounds__(512) void k_tile(TileArgs a, int64_t nblocks, int remap) {
+constexpr int kTileThreads = (sizeof(S) == 8 && OP == OP_LAP && U == 3) ? 512 : 1024;
+
+template <class S, int OP, int U>
+__global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, int64_t nblocks, int remap) {
   extern __shared__ __align__(16) char lds[];
   using R = TileRec<S, OP>;
   const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
@@ -1555,6 +1560,8 @@ hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int n
 template <class S, int OP>
 hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds, int64_t nblocks, int remap,
                          hipStream_t st) {
+  const int maxt = U == 1 ? kTileThreads<S, OP, 1> : U == 2 ? kTileThreads<S, OP, 2> : kTileThreads<S, OP, 3>;
+  if ((int)b.x > maxt) b.x = (unsigned)maxt;
   if (lds > 65536) {
     const void* fn = U == 1 ? reinterpret_cast<const void*>(&k_tile<S, OP, 1>)
                      : U == 2 ? reinterpret_cast<const void*>(&k_tile<S, OP, 2>)
@@ -1699,7 +1706,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   else if (dtype == DT_BF16)
     d = op == OP_LAP ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else
-    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 8} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
+    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 16} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;

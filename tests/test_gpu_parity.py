@@ -270,7 +270,8 @@ SHAPES += [dict(lds_tiles=3, tile_kb=kb, waves_per_block=w, slices_per_iter=u, b
                 xcd_remap=x, nt_stores=nt)
            for (kb, w, u, h, r, x, nt) in [(0, 4, 0, 0, 0, 0, 0), (64, 2, 3, 32, 16, 1, 2), (8, 1, 1, 1, 1, 2, 1),
                                            (24, 4, 2, 4, 8, 1, 1), (16, 2, 3, 1000, 1000, 2, 2),
-                                           (40, 1, 2, 7, 3, 1, 2)]]
+                                           (40, 1, 2, 7, 3, 1, 2), (160, 16, 0, 4, 8, 1, 0),
+                                           (48, 16, 3, 3, 8, 2, 0)]]
 # persistent double-buffered tiles: wave splits, workgroups per CU, lanes per node
 SHAPES += [dict(lds_tiles=1, tile_kb=kb, tile_waves=c, producer_waves=pw, tile_wgs_per_cu=g, lanes_per_node=p,
                 slices_per_iter=u, band_rows=h, run_nodes=r, xcd_remap=x, nt_stores=nt)
