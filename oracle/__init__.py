@@ -18,6 +18,9 @@ here in the readings listed in each module):
 * ``nabla`` -- gradient, divergence, Laplacian and the exact adjoints of
   gradient and divergence, applied as edge loops with scatter, plus the
   FP64 conservation sums.
+* ``remap`` -- target grids (regular "F" and octahedral "O" Gaussian grids)
+  and the linear interpolation of a field over the source triangles in 3-D
+  on the sphere (Section 4.3, Figures 4-6), with brute-force point location.
 
 Everything is FP64 NumPy, vectorised where a loop would be too slow for the
 large grids; no blocking or reordering beyond what each formula states.
@@ -27,3 +30,4 @@ from .grid import OGrid, gaussian_colatitudes, parse_grid_name  # noqa: F401
 from .mesh import OMesh, build_mesh  # noqa: F401
 from .dual import DualGeometry, build_dual  # noqa: F401
 from . import nabla  # noqa: F401
+from . import remap  # noqa: F401
