@@ -24,9 +24,10 @@ here:
   w_a f_a + w_b f_b + w_c f_c, level by level.
 * Points on an edge or at a node lie in several triangles; each gives the
   same value up to rounding (the weights of the nodes not shared are zero).
-  The oracle takes the containing triangle whose smallest weight is largest
-  (ties: the lowest triangle index), so its choice is deterministic; tests
-  compare values, not triangle indices.
+  A triangle counts as containing p when D > 0 and its smallest triple
+  product is >= -DET_TOL; the oracle takes the containing triangle whose
+  smallest weight is largest (ties: the lowest triangle index), so its
+  choice is deterministic; tests compare values, not triangle indices.
 
 Point location is brute force: every triangle is tested against every target
 point (in blocks of targets), which is slow but obviously complete.
@@ -39,8 +40,11 @@ import numpy as np
 
 from .grid import OGrid, _libm, gaussian_colatitudes
 
-# containment tolerance on the normalised weights (points on an edge)
-CONTAIN_TOL = 1e-12
+# containment tolerance on the triple products (points on an edge or at a
+# node): products of unit vectors carry rounding of about 1e-15, while the
+# normalised weights D_x / D carry that divided by D ~ h^2, too much for a
+# fixed tolerance on fine meshes
+DET_TOL = 1e-14
 
 
 class TargetGrid:
@@ -82,25 +86,28 @@ def _det(a, b, c):
     return np.einsum("...i,...i->...", a, np.cross(b, c))
 
 
+def triple_products(a, b, c, p):
+    """(D_a, D_b, D_c) of the module docstring, stacked on the last axis.
+    Arrays broadcast row-wise (last axis = xyz)."""
+    return np.stack([_det(p, b, c), _det(a, p, c), _det(a, b, p)], axis=-1)
+
+
 def triangle_weights(a, b, c, p):
     """Barycentric weights of the ray through p in the plane of (a, b, c):
-    (D_a, D_b, D_c) / D with the triple products of the module docstring,
-    and D itself.  Arrays broadcast row-wise (last axis = xyz)."""
-    da = _det(p, b, c)
-    db = _det(a, p, c)
-    dc = _det(a, b, p)
-    d = da + db + dc
+    (D_a, D_b, D_c) / D, and D itself."""
+    dd = triple_products(a, b, c, p)
+    d = dd[..., 0] + dd[..., 1] + dd[..., 2]
     with np.errstate(divide="ignore", invalid="ignore"):   # D = 0: ray in the plane
-        return np.stack([da, db, dc], axis=-1) / d[..., None], d
+        return dd / d[..., None], d
 
 
 def locate(src_xyz, tris, points, block=64):
     """For every point, the containing source triangle and its weights.
 
     Brute force: each block of points is tested against all triangles; among
-    the triangles with D > 0 and every weight >= -CONTAIN_TOL the one with
-    the largest smallest weight wins (lowest index on ties).  Raises if a
-    point lies in no triangle.
+    the triangles with D > 0 and every triple product >= -DET_TOL the one
+    with the largest smallest weight wins (lowest index on ties).  Raises if
+    a point lies in no triangle.
     Returns (tri [P] int64, nodes [P][3] int64, weights [P][3] float64)."""
     a = src_xyz[tris[:, 0]]
     b = src_xyz[tris[:, 1]]
@@ -109,11 +116,14 @@ def locate(src_xyz, tris, points, block=64):
     tri = np.empty(P, dtype=np.int64)
     for s in range(0, P, block):
         p = points[s:s + block][:, None, :]                   # [B,1,3]
-        w, d = triangle_weights(a[None], b[None], c[None], p)  # [B,T,3], [B,T]
+        dd = triple_products(a[None], b[None], c[None], p)     # [B,T,3]
+        d = dd.sum(axis=-1)
         # D = p . ((b - a) x (c - a)) > 0: the ray meets the front side
-        score = np.where(d > 0, w.min(axis=-1), -np.inf)
+        inside = (d > 0) & (dd.min(axis=-1) >= -DET_TOL)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            score = np.where(inside, dd.min(axis=-1) / d, -np.inf)
         best = np.argmax(score, axis=1)                        # first maximum
-        ok = score[np.arange(best.size), best] >= -CONTAIN_TOL
+        ok = np.isfinite(score[np.arange(best.size), best])
         if not ok.all():
             raise RuntimeError(f"points {np.nonzero(~ok)[0][:5] + s} lie in no triangle")
         tri[s:s + block] = best
