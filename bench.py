@@ -189,9 +189,51 @@ def run_gpu(args):
             ", ".join(f"{op} {per_op[op]['ms']:.3f}ms {per_op[op]['hbm_frac'] * 100:.0f}%" for op in OPS))
         del f, g, d, lp, fT, gT, outs
         torch.cuda.empty_cache()
+    if not args.skip_remap:
+        results["remap"] = run_remap(args, pa, mesh, f64)
     del refs, f64
     torch.cuda.empty_cache()
     return mesh, results
+
+
+def run_remap(args, pa, mesh, f64):
+    """Remap of the benchmark field to the regular Gaussian grid of half the
+    resolution (O1280 -> F640 by default): HIP-event time per call, and
+    algorithmic bytes = the source columns the tables reference (each read
+    once) + the target columns written + the tables (16 B of node indices and
+    4 weights of the dtype's weight type per target point)."""
+    import numpy as np
+    import torch
+
+    N = int(args.grid[1:])
+    target = f"F{max(1, N // 2)}"
+    t0 = time.time()
+    r = pa.Remap(mesh, target)
+    log(f"remap {args.grid} -> {target}: {r.npoints} points located in {time.time() - t0:.1f}s "
+        f"({r.nfallback} by exhaustive search)")
+    nsrc = int(np.unique(r.export()["nodes"]).size)
+    V, L, P = mesh.nnodes, args.levels, r.npoints
+    out = {"target": target, "npoints": P, "source_columns_read": nsrc}
+    for dname, dtype, esize in (("f64", torch.float64, 8), ("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        x = f64.to(dtype)
+        y = torch.empty((P, L), dtype=dtype, device=x.device)
+        for _ in range(max(1, args.warmup)):
+            r(x, out=y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            r(x, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        by = (nsrc + P) * L * esize + P * (16 + 4 * (8 if dname == "f64" else 4))
+        out[dname] = {"ms": round(ms, 4), "alg_GB": round(by / 1e9, 3), "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
+                      "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3),
+                      "point_levels_s": float(f"{P * L / (ms * 1e-3):.4g}")}
+        log(f"remap {dname}: {ms:.3f} ms, {out[dname]['GB_s']:.0f} GB/s algorithmic")
+        del x, y
+    r.close()
+    return out
 
 
 def run_batched(args):
@@ -307,6 +349,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=2)
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-remap", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -354,7 +397,8 @@ def main():
         "bf16": {"ms_per_step": res["bf16"]["ms_per_step"], "edge_updates_s": res["bf16"]["edge_updates_s"]},
         "f32_speedup_over_f64": round(res["f64"]["ms_per_step"] / f32["ms_per_step"], 3),
         "batched_o640": batched,
-        "detail": res,
+        "remap": res.get("remap"),
+        "detail": {k: v for k, v in res.items() if k != "remap"},
     }
     print(json.dumps(out))
 

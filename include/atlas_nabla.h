@@ -192,6 +192,44 @@ int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev,
                              const void* div, double* out_sum, double* out_abs,
                              void* stream);
 
+/* ---- grid-to-grid remapping (Section 4.3, Figures 4-6) ----------------------
+ * A field on the nodes of an O-grid mesh is interpolated to the points of a
+ * target grid, linearly over the source triangle each point lies in, in 3-D
+ * on the sphere: the ray from the centre through the target point p meets
+ * the flat triangle (a, b, c) (outward counter-clockwise) where the triple
+ * products D_a = det(p,b,c), D_b = det(a,p,c), D_c = det(a,b,p) are >= 0 with
+ * sum D > 0, and the weights are (D_a, D_b, D_c) / D.  Target grids: "F<M>",
+ * the regular Gaussian grid (2M rows at the roots of P_2M, 4M points per row
+ * at longitude 2 pi j / 4M), or "O<M>"; points numbered row by row from
+ * north to south, west to east. */
+typedef struct atlas_remap_s* atlas_remap_t;
+
+/* Locates every target point on the host (FP64) and, for a mesh built on a
+ * device, uploads the tables (P x 16 bytes of node indices and P x 32 / 16
+ * bytes of FP64 / FP32 weights).  The remap refers to `mesh`, which must
+ * outlive it.  *out owned by the caller; release with atlas_remap_free.
+ * Statuses: ATLAS_EINVAL (NULL arguments, bad target name), ATLAS_ENOMEM,
+ * ATLAS_ESHAPE (target too large), ATLAS_EHIP. */
+int atlas_remap_build(atlas_mesh_t mesh, const char* target, atlas_remap_t* out);
+void atlas_remap_free(atlas_remap_t remap);
+
+/* npoints: target points P; nfallback: points that needed the exhaustive
+ * search (0 on the octahedral meshes).  NULL pointers are skipped. */
+int atlas_remap_sizes(atlas_remap_t remap, int64_t* npoints, int64_t* nfallback);
+
+/* Host copies, caller-owned: nodes int32 [P][3], weights FP64 [P][3],
+ * target positions xyz FP64 [P][3] (unit vectors).  NULL skips an array. */
+int atlas_remap_export(atlas_remap_t remap, int32_t* nodes, double* weights, double* xyz);
+
+/* dst[t][k] = w_t0 src[n_t0][k] + w_t1 src[n_t1][k] + w_t2 src[n_t2][k]
+ * (in this order, with fused multiply-adds) for every target point t and
+ * level k.  src: device [V][nlev] of dtype (any alignment of the element
+ * size); dst: device [P][nlev], overwritten, must not overlap src.  FP64
+ * weights for ATLAS_F64, FP32 weights and arithmetic for ATLAS_F32 and
+ * ATLAS_BF16.  Asynchronous on `stream`. */
+int atlas_remap_apply(atlas_remap_t remap, int dtype, int32_t nlev, const void* src, void* dst,
+                      void* stream);
+
 /* ---- batched multi-tracer launch ------------------------------------------
  * Many fields with different level counts go through one persistent kernel
  * launch per operator.  Per tracer, the same arithmetic per output element
@@ -217,8 +255,10 @@ typedef struct {
 
 /* Launch shape.  Zero fields mean "library default". */
 typedef struct {
-  int32_t waves_per_block;  /* 1, 2, 4 or 8 (8: one-tile-per-workgroup LDS
-                               tiles only; other launches use at most 4)     */
+  int32_t waves_per_block;  /* 1, 2, 4, 8 or 16 (8 and 16: one-tile-per-
+                               workgroup LDS tiles only, 16 except for the
+                               three-slice FP64 Laplacian, which takes 8;
+                               other launches use at most 4)                 */
   int32_t nodes_per_wave;   /* node groups a wave handles per workgroup       */
   int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CU count     */
   int32_t xcd_remap;        /* 1: each XCD walks a contiguous part of the

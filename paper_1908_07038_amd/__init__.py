@@ -96,6 +96,11 @@ _SIGS = {
     "atlas_nabla_set_tune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(TuneShape)]),
     "atlas_nabla_describe": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, _I32, ctypes.POINTER(TuneShape),
                                             ctypes.c_char_p, _I32]),
+    "atlas_remap_build": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "atlas_remap_free": (None, [_P]),
+    "atlas_remap_sizes": (ctypes.c_int, [_P, _I64P, _I64P]),
+    "atlas_remap_export": (ctypes.c_int, [_P, _P, _P, _P]),
+    "atlas_remap_apply": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
 }
 
 
@@ -304,6 +309,59 @@ def laplacian(mesh, f, out=None, workspace=None):
     _check(lib().atlas_nabla_laplacian(mesh.handle, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), ws, _stream(f)))
     return out
+
+
+class Remap:
+    """Remapping of node fields of ``mesh`` to the points of a target grid
+    ("F<M>" or "O<M>") by linear interpolation over the source triangles in
+    3-D on the sphere (see atlas_remap_build).  Keep ``mesh`` alive while the
+    remap is used (the object holds a reference to it)."""
+
+    def __init__(self, mesh, target):
+        self.mesh = mesh
+        self.target = target
+        h = ctypes.c_void_p()
+        _check(lib().atlas_remap_build(mesh.handle, target.encode(), ctypes.byref(h)))
+        self._h = h
+        n, f = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().atlas_remap_sizes(h, ctypes.byref(n), ctypes.byref(f)))
+        self.npoints, self.nfallback = n.value, f.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().atlas_remap_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self):
+        """Host tables: nodes int32 [P][3], weights FP64 [P][3], xyz [P][3]."""
+        P = self.npoints
+        out = dict(nodes=np.empty((P, 3), np.int32), weights=np.empty((P, 3), np.float64),
+                   xyz=np.empty((P, 3), np.float64))
+        _check(lib().atlas_remap_export(self._h, *(_np_ptr(out[k]) for k in ("nodes", "weights", "xyz"))))
+        return out
+
+    def __call__(self, f, out=None):
+        """[V][L] source field -> [P][L] target field (same dtype)."""
+        import torch
+        nlev = _field(self.mesh, f, 1, "f")
+        if out is None:
+            out = torch.empty((self.npoints, nlev), dtype=f.dtype, device=f.device)
+        elif (not out.is_cuda or out.dtype != f.dtype or tuple(out.shape) != (self.npoints, nlev)
+              or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous device tensor [npoints][nlev] of the input dtype")
+        _check(lib().atlas_remap_apply(self._h, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _stream(f)))
+        return out
 
 
 def conservation(mesh, div):

@@ -47,7 +47,7 @@ def _commands():
            "-Wno-unused-command-line-argument"]
     objs = []
     cmds = []
-    for src, base in (("mesh_build.cpp", host), ("capi.cpp", host), ("kernels.hip", dev)):
+    for src, base in (("mesh_build.cpp", host), ("remap_build.cpp", host), ("capi.cpp", host), ("kernels.hip", dev)):
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
         cmds.append(base + inc + ["-c", os.path.join(CSRC, src), "-o", obj])

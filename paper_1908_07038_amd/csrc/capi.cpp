@@ -584,6 +584,115 @@ int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op, const atlas_
   return ATLAS_OK;
 }
 
+struct atlas_remap_s {
+  atlas_mesh_t mesh = nullptr;
+  RemapHost host;
+  int32_t* nodes = nullptr;   // device [P][4]
+  void* w64 = nullptr;        // device [P][4] FP64
+  void* w32 = nullptr;        // device [P][4] FP32
+  ~atlas_remap_s() {
+    if (mesh && mesh->device >= 0) {
+      DeviceGuard g(mesh->device);
+      for (void* p : {(void*)nodes, w64, w32})
+        if (p) (void)hipFree(p);
+    }
+  }
+};
+
+namespace {
+
+hipError_t upload_to(const void* data, size_t bytes, void** p) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*p, data, bytes, hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+int atlas_remap_build(atlas_mesh_t mesh, const char* target, atlas_remap_t* out) {
+  if (!out) return fail(ATLAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
+  if (!target) return fail(ATLAS_EINVAL, "target grid name is NULL");
+  if (parse_target_name(target, nullptr) < 1)
+    return fail(ATLAS_EINVAL, std::string("not a target grid name: '") + target + "'");
+  atlas_remap_s* r = nullptr;
+  try {
+    r = new atlas_remap_s();
+    r->mesh = mesh;
+    build_remap(mesh->host, target, r->host);
+    if (mesh->device >= 0) {
+      DeviceGuard g(mesh->device);
+      if (!g.ok) {
+        delete r;
+        return fail(ATLAS_EHIP, "cannot select the mesh's device");
+      }
+      const std::vector<float> w32 = to_f32(r->host.w);
+      hipError_t e = upload_to(r->host.nodes.data(), r->host.nodes.size() * sizeof(int32_t),
+                               reinterpret_cast<void**>(&r->nodes));
+      if (e == hipSuccess) e = upload_to(r->host.w.data(), r->host.w.size() * sizeof(double), &r->w64);
+      if (e == hipSuccess) e = upload_to(w32.data(), w32.size() * sizeof(float), &r->w32);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete r;
+        return e == hipErrorOutOfMemory ? fail(ATLAS_ENOMEM, "out of device memory for the remap tables")
+                                        : hip_fail(e, "remap tables");
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    delete r;
+    return fail(ATLAS_ENOMEM, "out of memory building the remap");
+  } catch (const std::length_error& e) {
+    delete r;
+    return fail(ATLAS_ESHAPE, e.what());
+  } catch (const std::exception& e) {
+    delete r;
+    return fail(ATLAS_EINVAL, e.what());
+  }
+  *out = r;
+  return ATLAS_OK;
+}
+
+void atlas_remap_free(atlas_remap_t remap) { delete remap; }
+
+int atlas_remap_sizes(atlas_remap_t remap, int64_t* npoints, int64_t* nfallback) {
+  if (!remap) return fail(ATLAS_EINVAL, "remap is NULL");
+  if (npoints) *npoints = remap->host.P;
+  if (nfallback) *nfallback = remap->host.fallback;
+  return ATLAS_OK;
+}
+
+int atlas_remap_export(atlas_remap_t remap, int32_t* nodes, double* weights, double* xyz) {
+  if (!remap) return fail(ATLAS_EINVAL, "remap is NULL");
+  const RemapHost& h = remap->host;
+  for (int64_t t = 0; t < h.P; ++t)
+    for (int j = 0; j < 3; ++j) {
+      if (nodes) nodes[3 * t + j] = h.nodes[4 * t + j];
+      if (weights) weights[3 * t + j] = h.w[4 * t + j];
+    }
+  if (xyz) std::memcpy(xyz, h.xyz.data(), h.xyz.size() * sizeof(double));
+  return ATLAS_OK;
+}
+
+int atlas_remap_apply(atlas_remap_t remap, int dtype, int32_t nlev, const void* src, void* dst, void* stream) {
+  if (!remap) return fail(ATLAS_EINVAL, "remap is NULL");
+  int rc = check_mesh_device(remap->mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  if ((rc = check_field(src, 1, es, "src"))) return rc;
+  if ((rc = check_field(dst, 1, es, "dst"))) return rc;
+  const size_t nin = (size_t)remap->mesh->host.V * nlev * es, nout = (size_t)remap->host.P * nlev * es;
+  if (overlaps(src, nin, dst, nout)) return fail(ATLAS_EINVAL, "dst overlaps src");
+  DeviceGuard g(remap->mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  const void* w = dtype == ATLAS_F64 ? remap->w64 : remap->w32;
+  hipError_t e = launch_remap(dtype, remap->nodes, w, remap->host.P, nlev, src, dst, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "remap");
+  return ATLAS_OK;
+}
+
 int atlas_nabla_describe(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev, atlas_tune_t* resolved, char* kernel,
                          int32_t len) {
   if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");

@@ -1352,6 +1352,78 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
   }
 }
 
+// ---- remapping: out[t][k] = w0 f[n0][k] + w1 f[n1][k] + w2 f[n2][k] ---------------
+//
+// Linear interpolation over the source triangle of each target point
+// (Section 4.3).  A wave serves 64 / P target points, P lanes each (P = nlev
+// for columns of at most 32 levels, else 64), lane t of a point taking levels
+// t, t + P, ...; U level slices are loaded before the arithmetic.  Blocks are
+// remapped so that each XCD walks a contiguous range of target points (whose
+// source columns are neighbours, so they stay in that XCD's L2).  The sum is
+// w0 f0, then + w1 f1, then + w2 f2, with fused multiply-adds.
+template <class S, int U>
+__global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes, const void* __restrict__ wv,
+                                               const S* __restrict__ in, S* __restrict__ out, int64_t P, int L,
+                                               int lanes, int64_t nblocks, int remap) {
+  using C = typename Traits<S>::C;
+  const C* __restrict__ w = static_cast<const C*>(wv);
+  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
+  if (lb >= nblocks) return;
+  const int W = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int G = 64 / lanes;
+  const int j = lane / lanes, tl = lane - j * lanes;
+  const int64_t t = (lb * W + wave) * G + j;
+  if (j >= G || t >= P) return;   // idle lanes; the kernel has no barrier
+  const int4 nd = *reinterpret_cast<const int4*>(nodes + 4 * t);
+  const C w0 = w[4 * t], w1 = w[4 * t + 1], w2 = w[4 * t + 2];
+  const S* __restrict__ f0 = in + (size_t)nd.x * (size_t)L;
+  const S* __restrict__ f1 = in + (size_t)nd.y * (size_t)L;
+  const S* __restrict__ f2 = in + (size_t)nd.z * (size_t)L;
+  S* __restrict__ o = out + (size_t)t * (size_t)L;
+  for (int k0 = tl; k0 < L; k0 += lanes * U) {
+    C v0[U], v1[U], v2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + lanes * u;
+      const int kc = k < L ? k : L - 1;
+      v0[u] = ld1(f0 + kc);
+      v1[u] = ld1(f1 + kc);
+      v2[u] = ld1(f2 + kc);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      C acc = w0 * v0[u];
+      acc = fma(w1, v1[u], acc);
+      acc = fma(w2, v2[u], acc);
+      const int k = k0 + lanes * u;
+      if (k < L) st1<false>(o + k, acc);
+    }
+  }
+}
+
+template <class S>
+hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in, void* out,
+                          hipStream_t st) {
+  const int lanes = nlev <= 32 ? nlev : 64;
+  const int G = 64 / lanes;
+  constexpr int W = 4;
+  const int64_t groups = (P + G - 1) / G;
+  const int64_t nblocks = (groups + W - 1) / W;
+  const int64_t grid = (nblocks + 7) / 8 * 8;
+  const int nsl = (nlev + lanes - 1) / lanes;
+  const int U = nsl < 3 ? nsl : 3;
+  const dim3 g((unsigned)grid), b(64 * W);
+  const S* src = static_cast<const S*>(in);
+  S* dst = static_cast<S*>(out);
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_remap<S, 1>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    case 2: hipLaunchKernelGGL((k_remap<S, 2>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    default: hipLaunchKernelGGL((k_remap<S, 3>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+  }
+  return hipGetLastError();
+}
+
 // ---- conservation: fixed-order FP64 sums of V_i div_ik --------------------------
 //
 // Workgroup b reduces nodes [b*chunk, (b+1)*chunk) for every level.  Wave w
@@ -1980,6 +2052,17 @@ hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder
     case DT_F64: return launch_batched_t<double>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
     case DT_F32: return launch_batched_t<float>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
     case DT_BF16: return launch_batched_t<bf16_t>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
+                        void* out, hipStream_t stream) {
+  if (P < 1 || nlev < 1 || (P + 15) / 16 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  switch (dtype) {
+    case DT_F64: return launch_remap_t<double>(nodes, w, P, nlev, in, out, stream);
+    case DT_F32: return launch_remap_t<float>(nodes, w, P, nlev, in, out, stream);
+    case DT_BF16: return launch_remap_t<bf16_t>(nodes, w, P, nlev, in, out, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -132,6 +132,12 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
                                const void* div, double* scratch, double* out_sum,
                                double* out_abs, hipStream_t stream);
 
+// Remapping: out[t][k] = sum_j w[t][j] in[nodes[t][j]][k] over P target
+// points; nodes [P][4] int32 and w [P][4] (FP64 for DT_F64, FP32 otherwise),
+// fourth entries unused.
+hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
+                        void* out, hipStream_t stream);
+
 // Batched persistent launch over a device table of work items.
 struct BatchItem {
   const void* in;

@@ -70,6 +70,10 @@ struct OpTables {
 // Parse "O<N>"; returns N or -1.
 int parse_grid_name(const std::string& name);
 
+// Colatitudes (ascending) of the n roots of P_n(cos t), n even: Newton in t
+// from pi (k + 0.75) / (n + 0.5), mirrored about the equator.
+void gaussian_colatitudes(int n, std::vector<double>& out);
+
 // Build grid, connectivity and dual geometry.  Throws std::runtime_error /
 // std::bad_alloc on failure.
 void build_host_mesh(int N, double radius, HostMesh& m);
@@ -124,5 +128,26 @@ struct HaloTiles {
 // std::runtime_error when a single node does not fit.
 void build_halo_tiles(const HostMesh& m, const OpTables& t, int ring, int band_rows, int run_nodes,
                       int64_t col_bytes, int64_t row_bytes, int64_t budget_bytes, HaloTiles& out);
+
+// Remapping from an O-grid mesh to the points of a target grid by linear
+// interpolation over the source triangles in 3-D on the sphere (see
+// remap_build.cpp): per target point the three nodes of the triangle its ray
+// meets and their barycentric weights.
+struct RemapHost {
+  std::string target;             // canonical target name, "F<M>" or "O<M>"
+  int64_t P = 0;                  // target points
+  std::vector<double> xyz;        // [P][3] unit vectors
+  std::vector<int32_t> nodes;     // [P][4]: three source nodes, 0 padding
+  std::vector<double> w;          // [P][4]: their weights, 0 padding
+  int64_t fallback = 0;           // points located by the exhaustive search
+};
+
+// Parse "F<M>" or "O<M>"; returns M (kind in *kind) or -1.
+int parse_target_name(const std::string& name, char* kind);
+
+// Target points and their source triangles and weights.  Throws
+// std::runtime_error when a point lies in no triangle (cannot happen on a
+// closed mesh) and std::bad_alloc when memory runs out.
+void build_remap(const HostMesh& src, const std::string& target, RemapHost& out);
 
 }  // namespace atlasnabla

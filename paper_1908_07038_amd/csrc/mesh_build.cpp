@@ -61,6 +61,8 @@ inline double tri_solid_angle(const V3& a, const V3& b, const V3& c) {
   return 2.0 * std::atan2(num, den);
 }
 
+}  // namespace
+
 // Roots of P_n(cos t), ascending in t.
 void gaussian_colatitudes(int n, std::vector<double>& out) {
   const int half = n / 2;
@@ -86,6 +88,8 @@ void gaussian_colatitudes(int n, std::vector<double>& out) {
   }
   for (int k = 0; k < half; ++k) out[n - 1 - k] = M_PI - out[k];
 }
+
+namespace {
 
 struct Tri {
   int32_t v[3];

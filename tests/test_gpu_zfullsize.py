@@ -115,6 +115,45 @@ def test_o1280_sampled_parity():
     assert (cs.abs() / ca).max().item() < 1e-13
 
 
+def test_o1280_to_f640_remap_sampled():
+    """Remap O1280 x 137 -> F640 (the benchmarked configuration) at ~400
+    sampled target points (random, polar rows, equator, row starts) against
+    the oracle's location restricted to nearby triangles; constants are
+    reproduced everywhere."""
+    from oracle import remap as Rm
+    print("O1280 -> F640 remap: building", flush=True)
+    M = pa.Mesh("O1280", radius=R, device=0)
+    m, _ = oracle_mesh(1280)
+    r = pa.Remap(M, "F640")
+    assert r.npoints == 1280 * 2560 and r.nfallback == 0
+    tg = Rm.TargetGrid("F640")
+    rng = np.random.default_rng(91)
+    n = 2560
+    pts = np.unique(np.concatenate([rng.choice(r.npoints, 300, replace=False), np.arange(0, 2 * n, 37),
+                                    r.npoints - 1 - np.arange(0, 2 * n, 41), 639 * n + np.arange(0, 2 * n, 53),
+                                    np.arange(0, r.npoints, 97 * n + 13)])).astype(np.int64)
+    _, nodes, w = Rm.locate_near(m.grid.xyz, m.tris, tg.xyz[pts], math.cos(0.01))
+    L = 137
+    co = M.coords()
+    s, trend = W.workload_o1280(co, nlev=L, device=DEV)
+    f64 = (s[:, None] + torch.from_numpy(trend).to(DEV)[None, :]).contiguous()
+    del s
+    for dt, tol in [(torch.float64, 1e-12), (torch.float32, 1e-5), (torch.bfloat16, 4e-3)]:
+        x = f64.to(dt)
+        y = r(x)
+        torch.cuda.synchronize()
+        got = rows(y, pts)
+        ref = np.zeros_like(got)
+        for j in range(3):
+            ref += w[:, j:j + 1] * rows(x, nodes[:, j])
+        err = rel(got, ref)
+        print(f"  remap {dt}: rel L2 {err:.3e}", flush=True)
+        assert err <= tol, (dt, err)
+        del x, y
+    ones = r(torch.ones((M.nnodes, 3), dtype=torch.float32, device=DEV))
+    assert (ones - 1).abs().max().item() < 1e-6
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_o640_adjoints(dtype):
     print(f"O640 x 137 adjoints {dtype}", flush=True)
