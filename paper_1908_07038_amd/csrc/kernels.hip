@@ -1355,13 +1355,16 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
 // ---- remapping: out[t][k] = w0 f[n0][k] + w1 f[n1][k] + w2 f[n2][k] ---------------
 //
 // Linear interpolation over the source triangle of each target point
-// (Section 4.3).  A wave serves 64 / P target points, P lanes each (P = nlev
-// for columns of at most 32 levels, else 64), lane t of a point taking levels
-// t, t + P, ...; U level slices are loaded before the arithmetic.  Blocks are
-// remapped so that each XCD walks a contiguous range of target points (whose
-// source columns are neighbours, so they stay in that XCD's L2).  The sum is
-// w0 f0, then + w1 f1, then + w2 f2, with fused multiply-adds.
-template <class S, int U>
+// (Section 4.3).  A wave serves 64 / P lane groups, P lanes each (P = nlev
+// for columns of at most 32 levels, else 64), and each group TP consecutive
+// target points, lane t of a group taking levels t, t + P, ...; the node
+// indices and weights of the TP points and then U level slices of all their
+// source columns are loaded before the arithmetic (more loads in flight for
+// the 4- and 2-byte types).  Blocks are remapped so that each XCD walks a
+// contiguous range of target points (whose source columns are neighbours, so
+// they stay in that XCD's L2).  The sum is w0 f0, then + w1 f1, then + w2 f2,
+// with fused multiply-adds.
+template <class S, int U, int TP>
 __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes, const void* __restrict__ wv,
                                                const S* __restrict__ in, S* __restrict__ out, int64_t P, int L,
                                                int lanes, int64_t nblocks, int remap) {
@@ -1373,55 +1376,74 @@ __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int G = 64 / lanes;
   const int j = lane / lanes, tl = lane - j * lanes;
-  const int64_t t = (lb * W + wave) * G + j;
-  if (j >= G || t >= P) return;   // idle lanes; the kernel has no barrier
-  const int4 nd = *reinterpret_cast<const int4*>(nodes + 4 * t);
-  const C w0 = w[4 * t], w1 = w[4 * t + 1], w2 = w[4 * t + 2];
-  const S* __restrict__ f0 = in + (size_t)nd.x * (size_t)L;
-  const S* __restrict__ f1 = in + (size_t)nd.y * (size_t)L;
-  const S* __restrict__ f2 = in + (size_t)nd.z * (size_t)L;
-  S* __restrict__ o = out + (size_t)t * (size_t)L;
+  if (j >= G) return;   // idle lanes; the kernel has no barrier
+  const int64_t t0 = ((lb * W + wave) * G + j) * TP;
+  if (t0 >= P) return;
+  int4 nd[TP];
+  C w0[TP], w1[TP], w2[TP];
+#pragma unroll
+  for (int q = 0; q < TP; ++q) {
+    const int64_t t = t0 + q < P ? t0 + q : P - 1;   // past the last point: reload it, store nothing
+    nd[q] = *reinterpret_cast<const int4*>(nodes + 4 * t);
+    w0[q] = w[4 * t];
+    w1[q] = w[4 * t + 1];
+    w2[q] = w[4 * t + 2];
+  }
   for (int k0 = tl; k0 < L; k0 += lanes * U) {
-    C v0[U], v1[U], v2[U];
+    C v0[TP][U], v1[TP][U], v2[TP][U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + lanes * u;
-      const int kc = k < L ? k : L - 1;
-      v0[u] = ld1(f0 + kc);
-      v1[u] = ld1(f1 + kc);
-      v2[u] = ld1(f2 + kc);
-    }
+    for (int q = 0; q < TP; ++q)
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      C acc = w0 * v0[u];
-      acc = fma(w1, v1[u], acc);
-      acc = fma(w2, v2[u], acc);
-      const int k = k0 + lanes * u;
-      if (k < L) st1<false>(o + k, acc);
-    }
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + lanes * u;
+        const int kc = k < L ? k : L - 1;
+        v0[q][u] = ld1(in + (size_t)nd[q].x * (size_t)L + kc);
+        v1[q][u] = ld1(in + (size_t)nd[q].y * (size_t)L + kc);
+        v2[q][u] = ld1(in + (size_t)nd[q].z * (size_t)L + kc);
+      }
+#pragma unroll
+    for (int q = 0; q < TP; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        C acc = w0[q] * v0[q][u];
+        acc = fma(w1[q], v1[q][u], acc);
+        acc = fma(w2[q], v2[q][u], acc);
+        const int k = k0 + lanes * u;
+        if (k < L && t0 + q < P) st1<false>(out + (size_t)(t0 + q) * (size_t)L + k, acc);
+      }
   }
 }
 
-template <class S>
-hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in, void* out,
-                          hipStream_t st) {
+template <class S, int TP>
+hipError_t launch_remap_tp(const int32_t* nodes, const void* w, int64_t P, int nlev, const S* src, S* dst,
+                           hipStream_t st) {
   const int lanes = nlev <= 32 ? nlev : 64;
   const int G = 64 / lanes;
   constexpr int W = 4;
-  const int64_t groups = (P + G - 1) / G;
+  const int64_t groups = (P + (int64_t)G * TP - 1) / ((int64_t)G * TP);
   const int64_t nblocks = (groups + W - 1) / W;
   const int64_t grid = (nblocks + 7) / 8 * 8;
   const int nsl = (nlev + lanes - 1) / lanes;
   const int U = nsl < 3 ? nsl : 3;
   const dim3 g((unsigned)grid), b(64 * W);
-  const S* src = static_cast<const S*>(in);
-  S* dst = static_cast<S*>(out);
   switch (U) {
-    case 1: hipLaunchKernelGGL((k_remap<S, 1>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
-    case 2: hipLaunchKernelGGL((k_remap<S, 2>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
-    default: hipLaunchKernelGGL((k_remap<S, 3>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    case 1: hipLaunchKernelGGL((k_remap<S, 1, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    case 2: hipLaunchKernelGGL((k_remap<S, 2, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    default: hipLaunchKernelGGL((k_remap<S, 3, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
   }
   return hipGetLastError();
+}
+
+// Target points per lane group (measured at O1280 x 137 -> F640): one for
+// FP64, two (columns of at most 32 levels) or four for 4- and 2-byte data.
+template <class S>
+hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in, void* out,
+                          hipStream_t st) {
+  const S* src = static_cast<const S*>(in);
+  S* dst = static_cast<S*>(out);
+  if constexpr (sizeof(S) == 8) return launch_remap_tp<S, 1>(nodes, w, P, nlev, src, dst, st);
+  else if (nlev <= 32) return launch_remap_tp<S, 2>(nodes, w, P, nlev, src, dst, st);
+  else return launch_remap_tp<S, 4>(nodes, w, P, nlev, src, dst, st);
 }
 
 // ---- conservation: fixed-order FP64 sums of V_i div_ik --------------------------
