@@ -156,6 +156,17 @@ int atlas_nabla_divergence(atlas_mesh_t mesh, int dtype, int32_t nlev,
 int atlas_nabla_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev,
                           const void* f, void* lap, void* workspace, void* stream);
 
+/* Gradient and Laplacian of one field in one pass: grad as
+ * atlas_nabla_gradient, lap as the fused atlas_nabla_laplacian, bitwise the
+ * same values (up to the sign of zero) -- the two-ring differences f_m - f_i
+ * serve both sums, and the field is read from memory once.  f: scalar
+ * [V][nlev]; grad: vector [V][nlev][2]; lap: scalar [V][nlev]; no two of
+ * them may overlap.  Runs as one kernel on the Laplacian's launch shape
+ * when that is the one-tile LDS form (the default for columns of more than
+ * 32 levels), else as the two calls one after the other. */
+int atlas_nabla_gradient_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                   const void* f, void* grad, void* lap, void* stream);
+
 /* Exact transpose of atlas_nabla_gradient for the plain Euclidean inner
  * product over all (node, level, component) entries:
  * sum(w * grad f) == sum(f * gradient_adjoint(w)).

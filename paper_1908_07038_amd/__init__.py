@@ -82,6 +82,7 @@ _SIGS = {
     "atlas_nabla_gradient_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_divergence_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_conservation": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_gradient_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_curl_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_batch_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TracerDesc), _I32,
@@ -362,6 +363,25 @@ class Remap:
         _check(lib().atlas_remap_apply(self._h, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), _stream(f)))
         return out
+
+
+def gradient_laplacian(mesh, f, out_grad=None, out_lap=None):
+    """(gradient(f), laplacian(f)) in one pass over f (same values as the two
+    calls, up to the sign of zero)."""
+    import torch
+    nlev = _field(mesh, f, 1, "f")
+    if out_grad is None:
+        out_grad = torch.empty((mesh.nnodes, nlev, 2), dtype=f.dtype, device=f.device)
+    if out_lap is None:
+        out_lap = torch.empty_like(f)
+    _field(mesh, out_grad, 2, "out_grad")
+    _field(mesh, out_lap, 1, "out_lap")
+    if out_grad.dtype != f.dtype or out_lap.dtype != f.dtype or out_grad.shape[1] != nlev or out_lap.shape[1] != nlev:
+        raise ValueError("outputs have the wrong dtype or shape")
+    _check(lib().atlas_nabla_gradient_laplacian(mesh.handle, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
+                                                ctypes.c_void_p(out_grad.data_ptr()),
+                                                ctypes.c_void_p(out_lap.data_ptr()), _stream(f)))
+    return out_grad, out_lap
 
 
 def conservation(mesh, div):

@@ -650,6 +650,7 @@ struct TileArgs {
   const char* rec;       // [V] node records in tile order (see tile_record_bytes)
   const void* in;
   void* out;
+  void* out2;            // OP_GRADLAP: the gradient ([V][L][2]); out gets the Laplacian
   int64_t ntiles;
   int32_t L;             // levels
   int32_t KL;            // levels per chunk (L: whole columns)
@@ -658,15 +659,18 @@ struct TileArgs {
 };
 
 // Node record of the tile path: coefficient row (8 pairs, ring 1; 24
-// weights, ring 2), LDS position row (8 or 24 uint16), node index (int32),
-// zero padding to 16 bytes.
+// weights, ring 2, followed for OP_GRADLAP by the gradient's 8 pairs), LDS
+// position row (8 or 24 uint16), node index (int32), zero padding to 16
+// bytes.
 template <class S, int OP>
 struct TileRec {
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
-  static constexpr bool kRing2 = OP == OP_LAP;
+  static constexpr bool kRing2 = OP == OP_LAP || OP == OP_GRADLAP;
+  static constexpr bool kGrad = OP == OP_GRADLAP;   // gradient pairs after the weights
   static constexpr int kEntries = kRing2 ? kLapStride : 8;
-  static constexpr uint32_t kCoefB = kRing2 ? kEntries * sizeof(C) : 8 * sizeof(C2);
+  static constexpr uint32_t kLapB = kEntries * sizeof(C);   // ring 2: the 24 weights
+  static constexpr uint32_t kCoefB = kRing2 ? kLapB + (kGrad ? 8 * sizeof(C2) : 0) : 8 * sizeof(C2);
   static constexpr uint32_t kLocB = 2 * kEntries;
   static constexpr uint32_t kIdOff = kCoefB + kLocB;
   static constexpr uint32_t kBytes = (kIdOff + 4 + 15) & ~15u;
@@ -898,6 +902,71 @@ __device__ __forceinline__ void tile_node2(const TileArgs& a, const char* lds, c
   for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
 }
 
+// One node of the fused gradient and two-ring Laplacian (OP_GRADLAP): the
+// differences f_m - f_i of the NS entries feed both sums; the first 7 entries
+// are the node's 1-ring neighbours in slot order (the two-ring tables are
+// ordered so), weighted by the gradient pairs (zero past the node's degree,
+// which add exact zeros).  Same slot-order arithmetic as tile_node2 and the
+// gradient's tile_node1.
+template <class S, int U, int NS>
+__device__ __forceinline__ void tile_node2g(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
+                                            const typename Traits<S>::C* w, const typename Traits<S>::C2* cf,
+                                            uint32_t obase, int klc, int lane) {
+  using C = typename Traits<S>::C;
+  constexpr uint32_t kEl = (uint32_t)sizeof(S);
+  const uint32_t lo = (uint32_t)lane * kEl;
+  uint32_t vb[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) vb[s] = so[s] + lo;
+  const uint32_t vx = xo + lo;
+  S* __restrict__ out = static_cast<S*>(a.out) + (size_t)(obase + (uint32_t)lane);
+  S* __restrict__ og = static_cast<S*>(a.out2) + 2 * (size_t)(obase + (uint32_t)lane);
+  auto step = [&](int kb) {
+    const uint32_t ko = (uint32_t)kb * kEl;
+    C v[U][NS], x0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = lds_elem<S, C>(lds, vb[s] + ko + 64u * kEl * u);
+      x0[u] = lds_elem<S, C>(lds, vx + ko + 64u * kEl * u);
+    }
+    C acc[U], ax[U], ay[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[u] = 0;
+      ax[u] = 0;
+      ay[u] = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const C d = v[u][s] - x0[u];
+        acc[u] = fma(w[s], d, acc[u]);
+        if (s < 7) {
+          ax[u] = fma(cf[s].x, d, ax[u]);
+          ay[u] = fma(cf[s].y, d, ay[u]);
+        }
+      }
+      keep(acc[u]);
+      keep(ax[u]);
+      keep(ay[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (kb + 64 * u + lane < klc) {
+        const size_t k = (size_t)(kb + 64 * u);
+        if (a.nt) {
+          st1<true>(out + k, acc[u]);
+          st2<true>(og + 2 * k, ax[u], ay[u]);
+        } else {
+          st1<false>(out + k, acc[u]);
+          st2<false>(og + 2 * k, ax[u], ay[u]);
+        }
+      }
+    }
+  };
+  step(0);
+  for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
+}
+
 // Copy of one tile (chunk) into an LDS buffer by W waves: the records as one
 // copy spread over the waves, then each column segment by one wave (segment
 // i by wave i mod W), so each wave sets up only its own copies.
@@ -986,7 +1055,18 @@ __device__ __forceinline__ void tile_eval(const TileArgs& a, const char* lds, in
     C w[R::kEntries - 1];
 #pragma unroll
     for (int q = 0; q < R::kEntries - 1; ++q) w[q] = lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C));
-    if (ne <= 18) {
+    if constexpr (R::kGrad) {
+      C2 cf[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + R::kLapB + q * (uint32_t)sizeof(C2));
+      if (ne <= 18) {
+        tile_offsets<S, 18>(lds, data_off, data_off, colB, pos, self, so, xo);
+        tile_node2g<S, U, 18>(a, lds, so, xo, w, cf, obase, klc, lane);
+      } else {
+        tile_offsets<S, R::kEntries - 1>(lds, data_off, data_off, colB, pos, self, so, xo);
+        tile_node2g<S, 1, R::kEntries - 1>(a, lds, so, xo, w, cf, obase, klc, lane);
+      }
+    } else if (ne <= 18) {
       tile_offsets<S, 18>(lds, data_off, data_off, colB, pos, self, so, xo);
       tile_node2<S, U, 18>(a, lds, so, xo, w, obase, klc, lane);
     } else {
@@ -1052,16 +1132,28 @@ __device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, in
     if constexpr (R::kRing2) {
       auto run = [&](auto ns) {
         constexpr int NS = decltype(ns)::value;
-        C acc = 0;
+        C acc = 0, ax = 0, ay = 0;
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           const uint32_t pos = (q & 1) ? (w32[q >> 1] >> 16) : (w32[q >> 1] & 0xffffu);
-          const C v = lds_elem<S, C>(lds, off(pos));
-          acc = fma(lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C)), v - x0, acc);
+          const C d = lds_elem<S, C>(lds, off(pos)) - x0;
+          acc = fma(lds_ld<C>(lds, ro + q * (uint32_t)sizeof(C)), d, acc);
+          if constexpr (R::kGrad) {
+            if (q < 7) {
+              const C2 cq = lds_ld<C2>(lds, ro + R::kLapB + q * (uint32_t)sizeof(C2));
+              ax = fma(cq.x, d, ax);
+              ay = fma(cq.y, d, ay);
+            }
+          }
         }
         if (ok) {
           if (a.nt) st1<true>(out + (size_t)o, acc);
           else st1<false>(out + (size_t)o, acc);
+          if constexpr (R::kGrad) {
+            S* og = static_cast<S*>(a.out2) + 2 * (size_t)o;
+            if (a.nt) st2<true>(og, ax, ay);
+            else st2<false>(og, ax, ay);
+          }
         }
       };
       if (__all(!ok || ne <= 18)) run(std::integral_constant<int, 18>());
@@ -1104,9 +1196,10 @@ __device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, in
 }
 
 // Up to 16 waves per workgroup (at most 128 registers per lane), 8 for the
-// three-slice FP64 Laplacian, which needs more registers.
+// three-slice FP64 Laplacian and the FP64 fused gradient and Laplacian,
+// which need more registers.
 template <class S, int OP, int U>
-constexpr int kTileThreads = (sizeof(S) == 8 && OP == OP_LAP && U == 3) ? 512 : 1024;
+constexpr int kTileThreads = (sizeof(S) == 8 && (OP == OP_GRADLAP || (OP == OP_LAP && U == 3))) ? 512 : 1024;
 
 template <class S, int OP, int U>
 __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, int64_t nblocks, int remap) {
@@ -1143,6 +1236,7 @@ __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, i
 template <class S, int OP>
 __global__ __launch_bounds__(256) void k_pack_records(const int32_t* __restrict__ order,
                                                       const void* __restrict__ coef,
+                                                      const void* __restrict__ coef2,
                                                       const uint16_t* __restrict__ loc, int64_t V,
                                                       uint32_t* __restrict__ rec) {
   using R = TileRec<S, OP>;
@@ -1153,7 +1247,10 @@ __global__ __launch_bounds__(256) void k_pack_records(const int32_t* __restrict_
   const uint32_t d = (uint32_t)(t - q * kDw);
   const int64_t i = order[q];
   uint32_t v = 0;
-  if (d < R::kCoefB / 4) v = static_cast<const uint32_t*>(coef)[i * (R::kCoefB / 4) + d];
+  constexpr uint32_t kC1 = R::kGrad ? R::kLapB / 4 : R::kCoefB / 4;   // dwords from coef
+  constexpr uint32_t kC2 = R::kCoefB / 4 - kC1;                       // dwords from coef2
+  if (d < kC1) v = static_cast<const uint32_t*>(coef)[i * kC1 + d];
+  else if (d < R::kCoefB / 4) v = static_cast<const uint32_t*>(coef2)[i * kC2 + (d - kC1)];
   else if (d < R::kIdOff / 4) v = reinterpret_cast<const uint32_t*>(loc)[i * (R::kLocB / 4) + (d - R::kCoefB / 4)];
   else if (d == R::kIdOff / 4) v = (uint32_t)i;
   rec[t] = v;
@@ -1718,6 +1815,7 @@ hipError_t launch_tiles_t(int op, const TileArgs& a, int U, uint32_t lds, const 
     case OP_GRADT: return launch_tile_u<S, OP_GRADT>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     case OP_DIVT: return launch_tile_u<S, OP_DIVT>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     case OP_LAP: return launch_tile_u<S, OP_LAP>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_GRADLAP: return launch_tile_u<S, OP_GRADLAP>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1794,13 +1892,14 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   // waves per workgroup of the one-tile form)
   struct Def { int mode, kb, rows, cw, pw, lanes, wpb; };
   const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT;
+  const bool lap = op == OP_LAP || op == OP_GRADLAP;   // the fused form takes the Laplacian's
   Def d;
   if (dtype == DT_F32)
-    d = op == OP_LAP ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+    d = lap ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else if (dtype == DT_BF16)
-    d = op == OP_LAP ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+    d = lap ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else
-    d = op == OP_LAP ? Def{3, 160, 4, 0, 0, 0, 16} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
+    d = lap ? Def{3, 160, 4, 0, 0, 0, 16} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;
@@ -1823,7 +1922,7 @@ TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   TileGeom g;
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
   const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
-  g.ring = op == OP_LAP ? 2 : 1;
+  g.ring = (op == OP_LAP || op == OP_GRADLAP) ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
   // the read-past tail behind a workgroup's buffers (one, or two for the
@@ -1906,6 +2005,8 @@ int64_t tile_record_bytes(int op, int dtype) {
   switch (op * 2 + (dtype == DT_F64 ? 1 : 0)) {
     case OP_LAP * 2: return TileRec<float, OP_LAP>::kBytes;
     case OP_LAP * 2 + 1: return TileRec<double, OP_LAP>::kBytes;
+    case OP_GRADLAP * 2: return TileRec<float, OP_GRADLAP>::kBytes;
+    case OP_GRADLAP * 2 + 1: return TileRec<double, OP_GRADLAP>::kBytes;
     default: return dtype == DT_F64 ? TileRec<double, OP_GRAD>::kBytes : TileRec<float, OP_GRAD>::kBytes;
   }
 }
@@ -1914,21 +2015,25 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
                              int64_t V, void* rec, hipStream_t stream) {
   const int64_t n = V * (tile_record_bytes(op, dtype) / 4);
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
-  const void* coef = op == OP_LAP ? t.lap_w : t.coef[op];
+  const void* coef = (op == OP_LAP || op == OP_GRADLAP) ? t.lap_w : t.coef[op];
+  const void* coef2 = op == OP_GRADLAP ? t.coef[OP_GRAD] : nullptr;
   uint32_t* r = static_cast<uint32_t*>(rec);
   const bool f64 = dtype == DT_F64;
   if (op == OP_LAP) {
-    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_LAP>), g, b, 0, stream, order, coef, loc, V, r);
-    else hipLaunchKernelGGL((k_pack_records<float, OP_LAP>), g, b, 0, stream, order, coef, loc, V, r);
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_LAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_LAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+  } else if (op == OP_GRADLAP) {
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
   } else {
-    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRAD>), g, b, 0, stream, order, coef, loc, V, r);
-    else hipLaunchKernelGGL((k_pack_records<float, OP_GRAD>), g, b, 0, stream, order, coef, loc, V, r);
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRAD>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_GRAD>), g, b, 0, stream, order, coef, coef2, loc, V, r);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
-                        void* out, const Shape& shape, int num_cus, hipStream_t stream) {
+                        void* out, const Shape& shape, int num_cus, hipStream_t stream, void* out2) {
   // the tiling's LDS footprint must be the one the kernel lays out
   const bool bf = dtype == DT_BF16;
   const int64_t es = dtype == DT_F64 ? 8 : bf ? 2 : 4;
@@ -1950,6 +2055,9 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   a.rec = static_cast<const char*>(rec);
   a.in = in;
   a.out = out;
+  a.out2 = out2;
+  if ((op == OP_GRADLAP) != (out2 != nullptr) || (op == OP_GRADLAP && shape.lds_tiles != 3))
+    return hipErrorInvalidValue;   // the fused form: one-tile workgroups, both outputs
   a.ntiles = dt.ntiles;
   a.L = nlev;
   a.KL = dt.KL;

@@ -62,7 +62,8 @@ struct OpTables {
   std::vector<double> curl;         // [V][8][2]  (c', d') with T_e = m_e x S_e for S_e; diag (A', B')
   std::vector<double> curlT;        // [V][8][2]  (c', d') of the reverse slot; diag (A', B')
   int lap_stride = kLapStride;      // entries per node in the two-ring table
-  std::vector<int32_t> lap_nbr;     // [V][lap_stride]: neighbours, then padding (i);
+  std::vector<int32_t> lap_nbr;     // [V][lap_stride]: neighbours (the 1-ring ones first, in
+                                    // slot order, then the rest by index), then padding (i);
                                     // entry lap_stride-1 holds the count
   std::vector<double> lap_w;        // [V][lap_stride]
 };

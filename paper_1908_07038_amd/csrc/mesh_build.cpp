@@ -542,7 +542,23 @@ void build_op_tables(const HostMesh& m, OpTables& t) {
         if (j != i) add_w((int32_t)j, -g);
       }
     }
+    // order: the 1-ring neighbours in slot order (so that a kernel can take
+    // the gradient from the first deg_i differences), then the rest by index
     std::sort(ring.begin(), ring.end(), [](const Entry& x, const Entry& y) { return x.node < y.node; });
+    {
+      std::vector<Entry> ord;
+      ord.reserve(ring.size());
+      for (int s = 0; s < deg_i; ++s)
+        for (const Entry& en : ring)
+          if (en.node == t.nbr8[kEll * i + s]) ord.push_back(en);
+      for (const Entry& en : ring) {
+        bool nb = false;
+        for (int s = 0; s < deg_i; ++s) nb = nb || en.node == t.nbr8[kEll * i + s];
+        if (!nb) ord.push_back(en);
+      }
+      if (ord.size() != ring.size()) throw std::runtime_error("two-ring stencil misses a neighbour");
+      ring.swap(ord);
+    }
     cnt[i] = (int32_t)ring.size();
     maxcnt = std::max(maxcnt, (int)ring.size());
     flat.insert(flat.end(), ring.begin(), ring.end());

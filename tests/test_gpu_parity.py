@@ -337,3 +337,37 @@ def test_bf16_unaligned_field_falls_back():
     torch.cuda.synchronize()
     assert torch.equal(pa.gradient(M, xu), ref)
     assert torch.equal(pa.laplacian(M, xu), lap_ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_gradient_laplacian_in_one_pass(dtype):
+    """The fused pass gives the two operators' values (up to the sign of
+    zero) at every level count -- whole 64-level slices, packed remainders,
+    level chunks, columns of at most 32 levels (the two calls one after the
+    other) -- and on every Laplacian launch shape it runs with; against the
+    oracle through the separate calls' parity."""
+    M = gpu_mesh(32)
+    codes = {torch.float64: pa.F64, torch.float32: pa.F32, torch.bfloat16: pa.BF16}
+    shapes = [None, dict(lds_tiles=3, tile_kb=16), dict(lds_tiles=3, tile_levels=50, waves_per_block=4),
+              dict(lds_tiles=3, tile_kb=24, slices_per_iter=1, band_rows=2), dict(lds_tiles=2)]
+    for L in (137, 96, 70, 40, 19, 1):
+        print(f"case gradient_laplacian L {L} {dtype}", flush=True)
+        x = torch.from_numpy(_input(32, L, 1, 31)).to(DEV).to(dtype)
+        for sh in shapes:
+            pa.set_tune(M, pa.OP_LAPLACIAN, codes[dtype], sh)
+            try:
+                g, lp = pa.gradient_laplacian(M, x)
+                g0 = pa.gradient(M, x)
+                l0 = pa.laplacian(M, x)
+                torch.cuda.synchronize()
+            finally:
+                pa.set_tune(M, pa.OP_LAPLACIAN, codes[dtype], None)
+            assert torch.equal(g + 0.0, g0 + 0.0), (L, sh)
+            assert torch.equal(lp + 0.0, l0 + 0.0), (L, sh)
+    # outputs given; overlapping outputs are refused
+    x = torch.from_numpy(_input(32, 137, 1, 32)).to(DEV).to(dtype)
+    g = torch.empty((M.nnodes, 137, 2), dtype=dtype, device=DEV)
+    lp = torch.empty((M.nnodes, 137), dtype=dtype, device=DEV)
+    assert pa.gradient_laplacian(M, x, g, lp)[0] is g
+    with pytest.raises(pa.AtlasError):
+        pa.gradient_laplacian(M, x, g, g.view(-1)[:M.nnodes * 137].view(M.nnodes, 137))
