@@ -177,8 +177,10 @@ def run_gpu(args):
         zt = torch.empty((V, L), dtype=dtype, device=dev)
         ut = torch.empty((V, L, 2), dtype=dtype, device=dev)
         extra = {}
+        dd = torch.empty((V, L), dtype=dtype, device=dev)
         for name, fn in (("curl", lambda: pa.curl(mesh, g, out=zt)),
-                         ("curl_adjoint", lambda: pa.curl_adjoint(mesh, d, out=ut))):
+                         ("curl_adjoint", lambda: pa.curl_adjoint(mesh, d, out=ut)),
+                         ("divergence_curl", lambda: pa.divergence_curl(mesh, g, dd, zt))):
             fn()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
@@ -187,11 +189,13 @@ def run_gpu(args):
             b.record()
             torch.cuda.synchronize()
             ms = a.elapsed_time(b) / args.steps
-            by = 3 * esize * V * L + GEOM_BYTES_PER_NODE * V
+            nel = 4 if name == "divergence_curl" else 3   # elements read + written per node-level
+            by = nel * esize * V * L + GEOM_BYTES_PER_NODE * V
+            sweeps_x = 2 if name == "divergence_curl" else 1
             extra[name] = {"ms": round(ms, 4), "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
                            "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3),
-                           "edge_updates_s": float(f"{E * L / (ms * 1e-3):.4g}")}
-        del zt, ut
+                           "edge_updates_s": float(f"{sweeps_x * E * L / (ms * 1e-3):.4g}")}
+        del zt, ut, dd
         cs, ca = calls["conservation"]()
         cons = float((cs.abs() / ca).max().item())
         outs = {"gradient": g, "divergence": d, "laplacian": lp, "gradient_adjoint": fT,

@@ -188,6 +188,16 @@ int atlas_nabla_divergence_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
 int atlas_nabla_curl(atlas_mesh_t mesh, int dtype, int32_t nlev,
                      const void* uv, void* zeta, void* stream);
 
+/* Divergence and curl (vertical vorticity) of one vector field in one pass,
+ * bitwise the values of atlas_nabla_divergence and atlas_nabla_curl (up to
+ * the sign of zero); the field is read from memory once.  uv: vector
+ * [V][nlev][2]; div, zeta: scalar [V][nlev]; no two of them may overlap.
+ * One kernel on the divergence's launch shape when that is the one-tile LDS
+ * form (the default for columns of more than 32 levels), else the two calls
+ * one after the other. */
+int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                const void* uv, void* div, void* zeta, void* stream);
+
 /* Exact transpose of atlas_nabla_curl.
  * z: scalar [V][nlev] -> uvbar: vector [V][nlev][2]. */
 int atlas_nabla_curl_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,

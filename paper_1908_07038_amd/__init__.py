@@ -83,6 +83,7 @@ _SIGS = {
     "atlas_nabla_divergence_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_conservation": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_gradient_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_divergence_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_curl_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_batch_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TracerDesc), _I32,
@@ -382,6 +383,25 @@ def gradient_laplacian(mesh, f, out_grad=None, out_lap=None):
                                                 ctypes.c_void_p(out_grad.data_ptr()),
                                                 ctypes.c_void_p(out_lap.data_ptr()), _stream(f)))
     return out_grad, out_lap
+
+
+def divergence_curl(mesh, uv, out_div=None, out_curl=None):
+    """(divergence(uv), curl(uv)) in one pass over uv (same values as the two
+    calls, up to the sign of zero)."""
+    import torch
+    nlev = _field(mesh, uv, 2, "uv")
+    if out_div is None:
+        out_div = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+    if out_curl is None:
+        out_curl = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+    _field(mesh, out_div, 1, "out_div")
+    _field(mesh, out_curl, 1, "out_curl")
+    if out_div.dtype != uv.dtype or out_curl.dtype != uv.dtype or out_div.shape[1] != nlev or out_curl.shape[1] != nlev:
+        raise ValueError("outputs have the wrong dtype or shape")
+    _check(lib().atlas_nabla_divergence_curl(mesh.handle, _dtype_code(uv), nlev, ctypes.c_void_p(uv.data_ptr()),
+                                             ctypes.c_void_p(out_div.data_ptr()),
+                                             ctypes.c_void_p(out_curl.data_ptr()), _stream(uv)))
+    return out_div, out_curl
 
 
 def conservation(mesh, div):

@@ -573,6 +573,50 @@ int atlas_nabla_gradient_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev, c
   return run_op(mesh, OP_LAP, dtype, nlev, f, lap, stream);
 }
 
+int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* div, void* zeta,
+                                void* stream) {
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  const int64_t V = mesh->host.V;
+  if ((int64_t)nlev * V > (int64_t)UINT32_MAX) return fail(ATLAS_ESHAPE, "nnodes * nlev exceeds 2^32 - 1");
+  if ((rc = check_field(uv, 2, es, "uv"))) return rc;
+  if ((rc = check_field(div, 1, es, "div"))) return rc;
+  if ((rc = check_field(zeta, 1, es, "zeta"))) return rc;
+  const size_t n1 = (size_t)V * nlev * es;
+  if (overlaps(uv, 2 * n1, div, n1) || overlaps(uv, 2 * n1, zeta, n1) || overlaps(div, n1, zeta, n1))
+    return fail(ATLAS_EINVAL, "uv, div and zeta must not overlap");
+  DeviceGuard g(mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  // one pass on the divergence's launch shape when that is the one-tile LDS
+  // form; otherwise the two operators run one after the other
+  const Shape sh = resolve_shape(OP_DIVCURL, dtype, nlev, mesh->shape[OP_DIV][dtype]);
+  TileGeom tg;
+  if (sh.lds_tiles == 3 && uses_tiles(OP_DIVCURL, dtype, nlev, sh)) tg = tile_geom(OP_DIVCURL, dtype, nlev, sh);
+  if (dtype == ATLAS_BF16 && ((uintptr_t)uv & 3u)) tg.KL = 0;
+  if (tg.KL > 0) {
+    DevTiles dt;
+    const void* rec = nullptr;
+    try {
+      dt = mesh->tiles(tg, sh);
+      dt.KL = tg.KL;
+      dt.nchunks = tg.nchunks;
+      rec = mesh->tile_records(tg, sh, dt, OP_DIVCURL, dtype, (hipStream_t)stream);
+    } catch (const std::bad_alloc&) {
+      return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
+    } catch (const std::exception& ex) {
+      return fail(ATLAS_EHIP, ex.what());
+    }
+    hipError_t e = launch_tiles(OP_DIVCURL, dtype, dt, rec, nlev, uv, div, sh, mesh->num_cus, (hipStream_t)stream, zeta);
+    if (e != hipSuccess) return hip_fail(e, "divergence_curl");
+    return ATLAS_OK;
+  }
+  if ((rc = run_op(mesh, OP_DIV, dtype, nlev, uv, div, stream))) return rc;
+  return run_op(mesh, OP_CURL, dtype, nlev, uv, zeta, stream);
+}
+
 int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* div, double* out_sum,
                              double* out_abs, void* stream) {
   int rc = check_mesh_device(mesh);

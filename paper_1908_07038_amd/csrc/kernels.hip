@@ -322,7 +322,7 @@ template <class S, int OP>
 struct WinT {
   using C = typename Traits<S>::C;
   using C2 = typename Traits<S>::C2;
-  static constexpr bool kVecIn = (OP == OP_DIV || OP == OP_GRADT);
+  static constexpr bool kVecIn = (OP == OP_DIV || OP == OP_GRADT || OP == OP_DIVCURL);
   using X = typename std::conditional<kVecIn, C2, C>::type;
   static __device__ __forceinline__ X ld(const S* __restrict__ in, uint32_t idx) {
     if constexpr (kVecIn) return ld2(in + 2 * (size_t)idx);
@@ -658,8 +658,9 @@ struct TileArgs {
   int32_t nt;
 };
 
-// Node record of the tile path: coefficient row (8 pairs, ring 1; 24
-// weights, ring 2, followed for OP_GRADLAP by the gradient's 8 pairs), LDS
+// Node record of the tile path: coefficient row (8 pairs, ring 1, followed
+// for OP_DIVCURL by the curl's 8 pairs; 24 weights, ring 2, followed for
+// OP_GRADLAP by the gradient's 8 pairs), LDS
 // position row (8 or 24 uint16), node index (int32), zero padding to 16
 // bytes.
 template <class S, int OP>
@@ -668,13 +669,15 @@ struct TileRec {
   using C2 = typename Traits<S>::C2;
   static constexpr bool kRing2 = OP == OP_LAP || OP == OP_GRADLAP;
   static constexpr bool kGrad = OP == OP_GRADLAP;   // gradient pairs after the weights
+  static constexpr bool kDual = OP == OP_DIVCURL;    // curl pairs after the divergence pairs
   static constexpr int kEntries = kRing2 ? kLapStride : 8;
   static constexpr uint32_t kLapB = kEntries * sizeof(C);   // ring 2: the 24 weights
-  static constexpr uint32_t kCoefB = kRing2 ? kLapB + (kGrad ? 8 * sizeof(C2) : 0) : 8 * sizeof(C2);
+  static constexpr uint32_t kCoefB = kRing2 ? kLapB + (kGrad ? 8 * sizeof(C2) : 0)
+                                            : 8 * sizeof(C2) * (kDual ? 2 : 1);
   static constexpr uint32_t kLocB = 2 * kEntries;
   static constexpr uint32_t kIdOff = kCoefB + kLocB;
   static constexpr uint32_t kBytes = (kIdOff + 4 + 15) & ~15u;
-  static constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT) ? 2 : 1;
+  static constexpr int kCin = (OP == OP_DIV || OP == OP_GRADT || OP == OP_DIVCURL) ? 2 : 1;
 };
 
 constexpr int kLocCountShift = 11;
@@ -967,6 +970,53 @@ __device__ __forceinline__ void tile_node2g(const TileArgs& a, const char* lds, 
   for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
 }
 
+// One node of the divergence and the curl of one vector field (OP_DIVCURL):
+// the same loads feed the divergence-form sums with the divergence pairs
+// (out) and with the curl pairs (out2), each exactly as tile_node1 computes
+// it for that operator.
+template <class S, int U, int DEG>
+__device__ __forceinline__ void tile_node1d(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
+                                            const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
+                                            const typename Traits<S>::C2* cf2, typename Traits<S>::C2 dg2,
+                                            uint32_t obase, int klc, int lane) {
+  using X = typename WinT<S, OP_DIVCURL>::X;
+  using C = typename Traits<S>::C;
+  constexpr uint32_t kEl = (uint32_t)sizeof(S) * 2;
+  const uint32_t lo = (uint32_t)lane * kEl;
+  uint32_t vb[DEG];
+#pragma unroll
+  for (int s = 0; s < DEG; ++s) vb[s] = so[s] + lo;
+  const uint32_t vx = xo + lo;
+  S* __restrict__ out = static_cast<S*>(a.out) + (size_t)(obase + (uint32_t)lane);
+  S* __restrict__ oz = static_cast<S*>(a.out2) + (size_t)(obase + (uint32_t)lane);
+  auto step = [&](int kb) {
+    const uint32_t ko = (uint32_t)kb * kEl;
+    X v[U][DEG], x0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int s = 0; s < DEG; ++s) v[u][s] = lds_elem<S, X>(lds, vb[s] + ko + 64u * kEl * u);
+      x0[u] = lds_elem<S, X>(lds, vx + ko + 64u * kEl * u);
+    }
+    C r0[U], z0[U], unused;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      win_combine<S, OP_DIVCURL, DEG>(x0[u], v[u], cf, dg, r0[u], unused);
+      win_combine<S, OP_DIVCURL, DEG>(x0[u], v[u], cf2, dg2, z0[u], unused);
+      keep(r0[u]);
+      keep(z0[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (kb + 64 * u + lane < klc) {
+        win_store<S, OP_DIVCURL>(out + kb, 64u * u, a.nt, r0[u], 0);
+        win_store<S, OP_DIVCURL>(oz + kb, 64u * u, a.nt, z0[u], 0);
+      }
+  };
+  step(0);
+  for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
+}
+
 // Copy of one tile (chunk) into an LDS buffer by W waves: the records as one
 // copy spread over the waves, then each column segment by one wave (segment
 // i by wave i mod W), so each wave sets up only its own copies.
@@ -1079,6 +1129,20 @@ __device__ __forceinline__ void tile_eval(const TileArgs& a, const char* lds, in
     for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
     const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
     tile_offsets<S, 7>(lds, data_off, data_off, colB, pos, self, so, xo);
+    if constexpr (R::kDual) {
+      C2 cf2[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) cf2[q] = lds_ld<C2>(lds, ro + (8 + q) * (uint32_t)sizeof(C2));
+      const C2 dg2 = lds_ld<C2>(lds, ro + 15 * (uint32_t)sizeof(C2));
+      switch (ne) {
+        case 6: tile_node1d<S, U, 6>(a, lds, so, xo, cf, dg, cf2, dg2, obase, klc, lane); break;
+        case 5: tile_node1d<S, 1, 5>(a, lds, so, xo, cf, dg, cf2, dg2, obase, klc, lane); break;
+        case 7: tile_node1d<S, 1, 7>(a, lds, so, xo, cf, dg, cf2, dg2, obase, klc, lane); break;
+        case 4: tile_node1d<S, 1, 4>(a, lds, so, xo, cf, dg, cf2, dg2, obase, klc, lane); break;
+        default: tile_node1d<S, 1, 3>(a, lds, so, xo, cf, dg, cf2, dg2, obase, klc, lane); break;
+      }
+      return;
+    }
     switch (ne) {
       case 6: tile_node1<S, OP, U, 6>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
       case 5: tile_node1<S, OP, 1, 5>(a, lds, so, xo, cf, dg, obase, klc, lane); break;
@@ -1159,36 +1223,46 @@ __device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, in
       if (__all(!ok || ne <= 18)) run(std::integral_constant<int, 18>());
       else run(std::integral_constant<int, NE>());
     } else {
-      C2 cf[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + q * (uint32_t)sizeof(C2));
-      const C2 dg = lds_ld<C2>(lds, ro + 7 * (uint32_t)sizeof(C2));
       X v[7];
 #pragma unroll
       for (int q = 0; q < 7; ++q) {
         const uint32_t pos = (q & 1) ? (w32[q >> 1] >> 16) : (w32[q >> 1] & 0xffffu);
         v[q] = lds_elem<S, X>(lds, off(pos));
       }
-      C r0, r1;
-      if (__all(!ok || ne == 6)) {
-        win_combine<S, OP, 6>(x0, v, cf, dg, r0, r1);
-      } else {
-        // per-lane degree: slots past ne leave the sums unchanged
-        C a0, a1, b0, b1;
-        win_combine<S, OP, 3>(x0, v, cf, dg, b0, b1);
+      const bool six = __all(!ok || ne == 6);
+      // the sums with the coefficient row at byte cb (8 pairs: 7 slots and
+      // the diagonal); per-lane degree: slots past ne leave the sums unchanged
+      auto combine = [&](uint32_t cb, C& r0, C& r1) {
+        C2 cf[7];
 #pragma unroll
-        for (int d = 4; d <= 7; ++d) {
-          if (d == 4) win_combine<S, OP, 4>(x0, v, cf, dg, a0, a1);
-          if (d == 5) win_combine<S, OP, 5>(x0, v, cf, dg, a0, a1);
-          if (d == 6) win_combine<S, OP, 6>(x0, v, cf, dg, a0, a1);
-          if (d == 7) win_combine<S, OP, 7>(x0, v, cf, dg, a0, a1);
-          if (ne >= d) {
-            b0 = a0;
-            b1 = a1;
+        for (int q = 0; q < 7; ++q) cf[q] = lds_ld<C2>(lds, ro + cb + q * (uint32_t)sizeof(C2));
+        const C2 dg = lds_ld<C2>(lds, ro + cb + 7 * (uint32_t)sizeof(C2));
+        if (six) {
+          win_combine<S, OP, 6>(x0, v, cf, dg, r0, r1);
+        } else {
+          C a0, a1, b0, b1;
+          win_combine<S, OP, 3>(x0, v, cf, dg, b0, b1);
+#pragma unroll
+          for (int d = 4; d <= 7; ++d) {
+            if (d == 4) win_combine<S, OP, 4>(x0, v, cf, dg, a0, a1);
+            if (d == 5) win_combine<S, OP, 5>(x0, v, cf, dg, a0, a1);
+            if (d == 6) win_combine<S, OP, 6>(x0, v, cf, dg, a0, a1);
+            if (d == 7) win_combine<S, OP, 7>(x0, v, cf, dg, a0, a1);
+            if (ne >= d) {
+              b0 = a0;
+              b1 = a1;
+            }
           }
+          r0 = b0;
+          r1 = b1;
         }
-        r0 = b0;
-        r1 = b1;
+      };
+      C r0, r1;
+      combine(0, r0, r1);
+      if constexpr (R::kDual) {
+        C z0, z1;
+        combine(8 * (uint32_t)sizeof(C2), z0, z1);
+        if (ok) win_store<S, OP>(static_cast<S*>(a.out2), o, a.nt, z0, z1);
       }
       if (ok) win_store<S, OP>(out, o, a.nt, r0, r1);
     }
@@ -1199,7 +1273,8 @@ __device__ __forceinline__ void tile_tail(const TileArgs& a, const char* lds, in
 // three-slice FP64 Laplacian and the FP64 fused gradient and Laplacian,
 // which need more registers.
 template <class S, int OP, int U>
-constexpr int kTileThreads = (sizeof(S) == 8 && (OP == OP_GRADLAP || (OP == OP_LAP && U == 3))) ? 512 : 1024;
+constexpr int kTileThreads =
+    (sizeof(S) == 8 && (OP == OP_GRADLAP || OP == OP_DIVCURL || (OP == OP_LAP && U == 3))) ? 512 : 1024;
 
 template <class S, int OP, int U>
 __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, int64_t nblocks, int remap) {
@@ -1247,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_pack_records(const int32_t* __restrict_
   const uint32_t d = (uint32_t)(t - q * kDw);
   const int64_t i = order[q];
   uint32_t v = 0;
-  constexpr uint32_t kC1 = R::kGrad ? R::kLapB / 4 : R::kCoefB / 4;   // dwords from coef
+  constexpr uint32_t kC1 = R::kGrad ? R::kLapB / 4 : R::kDual ? R::kCoefB / 8 : R::kCoefB / 4;   // from coef
   constexpr uint32_t kC2 = R::kCoefB / 4 - kC1;                       // dwords from coef2
   if (d < kC1) v = static_cast<const uint32_t*>(coef)[i * kC1 + d];
   else if (d < R::kCoefB / 4) v = static_cast<const uint32_t*>(coef2)[i * kC2 + (d - kC1)];
@@ -1816,6 +1891,7 @@ hipError_t launch_tiles_t(int op, const TileArgs& a, int U, uint32_t lds, const 
     case OP_DIVT: return launch_tile_u<S, OP_DIVT>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     case OP_LAP: return launch_tile_u<S, OP_LAP>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     case OP_GRADLAP: return launch_tile_u<S, OP_GRADLAP>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
+    case OP_DIVCURL: return launch_tile_u<S, OP_DIVCURL>(a, U, g, b, lds, nblocks, sh.xcd_remap, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1891,7 +1967,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   // (mode, KiB, tile rows, computing waves, copying waves, lanes per node,
   // waves per workgroup of the one-tile form)
   struct Def { int mode, kb, rows, cw, pw, lanes, wpb; };
-  const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT;
+  const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL;
   const bool lap = op == OP_LAP || op == OP_GRADLAP;   // the fused form takes the Laplacian's
   Def d;
   if (dtype == DT_F32)
@@ -1921,7 +1997,7 @@ bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   TileGeom g;
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
   g.ring = (op == OP_LAP || op == OP_GRADLAP) ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
@@ -1992,7 +2068,7 @@ int tile_slices(int KL, const Shape& sh) {
 
 int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U) {
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
   // a step reads 64 U levels (64 on the single-slice paths) from level 0 on:
   // past a chunk of k levels up to round_up(k, 64 U) - k levels
   const int64_t step = 64 * (int64_t)U;
@@ -2007,6 +2083,8 @@ int64_t tile_record_bytes(int op, int dtype) {
     case OP_LAP * 2 + 1: return TileRec<double, OP_LAP>::kBytes;
     case OP_GRADLAP * 2: return TileRec<float, OP_GRADLAP>::kBytes;
     case OP_GRADLAP * 2 + 1: return TileRec<double, OP_GRADLAP>::kBytes;
+    case OP_DIVCURL * 2: return TileRec<float, OP_DIVCURL>::kBytes;
+    case OP_DIVCURL * 2 + 1: return TileRec<double, OP_DIVCURL>::kBytes;
     default: return dtype == DT_F64 ? TileRec<double, OP_GRAD>::kBytes : TileRec<float, OP_GRAD>::kBytes;
   }
 }
@@ -2015,8 +2093,8 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
                              int64_t V, void* rec, hipStream_t stream) {
   const int64_t n = V * (tile_record_bytes(op, dtype) / 4);
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
-  const void* coef = (op == OP_LAP || op == OP_GRADLAP) ? t.lap_w : t.coef[op];
-  const void* coef2 = op == OP_GRADLAP ? t.coef[OP_GRAD] : nullptr;
+  const void* coef = (op == OP_LAP || op == OP_GRADLAP) ? t.lap_w : op == OP_DIVCURL ? t.coef[OP_DIV] : t.coef[op];
+  const void* coef2 = op == OP_GRADLAP ? t.coef[OP_GRAD] : op == OP_DIVCURL ? t.coef[OP_CURL] : nullptr;
   uint32_t* r = static_cast<uint32_t*>(rec);
   const bool f64 = dtype == DT_F64;
   if (op == OP_LAP) {
@@ -2025,6 +2103,9 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
   } else if (op == OP_GRADLAP) {
     if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
     else hipLaunchKernelGGL((k_pack_records<float, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+  } else if (op == OP_DIVCURL) {
+    if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_DIVCURL>), g, b, 0, stream, order, coef, coef2, loc, V, r);
+    else hipLaunchKernelGGL((k_pack_records<float, OP_DIVCURL>), g, b, 0, stream, order, coef, coef2, loc, V, r);
   } else {
     if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRAD>), g, b, 0, stream, order, coef, coef2, loc, V, r);
     else hipLaunchKernelGGL((k_pack_records<float, OP_GRAD>), g, b, 0, stream, order, coef, coef2, loc, V, r);
@@ -2037,7 +2118,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   // the tiling's LDS footprint must be the one the kernel lays out
   const bool bf = dtype == DT_BF16;
   const int64_t es = dtype == DT_F64 ? 8 : bf ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
   const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
   const int U3 = tile_slices(dt.KL, shape);
@@ -2056,8 +2137,9 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   a.in = in;
   a.out = out;
   a.out2 = out2;
-  if ((op == OP_GRADLAP) != (out2 != nullptr) || (op == OP_GRADLAP && shape.lds_tiles != 3))
-    return hipErrorInvalidValue;   // the fused form: one-tile workgroups, both outputs
+  const bool two = op == OP_GRADLAP || op == OP_DIVCURL;
+  if (two != (out2 != nullptr) || (two && shape.lds_tiles != 3))
+    return hipErrorInvalidValue;   // the one-pass forms: one-tile workgroups, both outputs
   a.ntiles = dt.ntiles;
   a.L = nlev;
   a.KL = dt.KL;

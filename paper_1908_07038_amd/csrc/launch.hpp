@@ -17,6 +17,8 @@ inline int kernel_op(int op) { return op == OP_CURL ? OP_DIV : op == OP_CURLT ? 
 // Gradient and two-ring Laplacian of one field in one pass over LDS tiles
 // (one-tile form only): an internal kernel operator beyond the public ones.
 constexpr int OP_GRADLAP = OP_COUNT;
+// Divergence and curl of one vector field in one pass (one-tile form only).
+constexpr int OP_DIVCURL = OP_COUNT + 1;
 enum Dtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 
 // Device tables of one mesh for one coefficient precision (FP64 for DT_F64,
@@ -120,7 +122,8 @@ int tile_slices(int KL, const Shape& sh);
 // order: coefficients, LDS positions, node index).
 hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,
                              int64_t V, void* rec, hipStream_t stream);
-// out2: the gradient output of OP_GRADLAP (out: its Laplacian), else NULL.
+// out2: the gradient output of OP_GRADLAP (out: its Laplacian), the curl
+// output of OP_DIVCURL (out: its divergence), else NULL.
 hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
                         void* out, const Shape& shape, int num_cus, hipStream_t stream, void* out2 = nullptr);
 

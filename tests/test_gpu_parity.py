@@ -371,3 +371,32 @@ def test_gradient_laplacian_in_one_pass(dtype):
     assert pa.gradient_laplacian(M, x, g, lp)[0] is g
     with pytest.raises(pa.AtlasError):
         pa.gradient_laplacian(M, x, g, g.view(-1)[:M.nnodes * 137].view(M.nnodes, 137))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_divergence_curl_in_one_pass(dtype):
+    """Divergence and curl of one vector field in one pass give the two
+    calls' values (up to the sign of zero) at every level count and on the
+    divergence launch shapes it runs with."""
+    M = gpu_mesh(32)
+    codes = {torch.float64: pa.F64, torch.float32: pa.F32, torch.bfloat16: pa.BF16}
+    shapes = [None, dict(lds_tiles=3, tile_kb=16), dict(lds_tiles=3, tile_levels=50, waves_per_block=4),
+              dict(lds_tiles=3, tile_kb=24, slices_per_iter=1, band_rows=2), dict(lds_tiles=2)]
+    for L in (137, 96, 70, 40, 19, 1):
+        print(f"case divergence_curl L {L} {dtype}", flush=True)
+        uv = torch.from_numpy(_input(32, L, 2, 33)).to(DEV).to(dtype)
+        for sh in shapes:
+            pa.set_tune(M, pa.OP_DIVERGENCE, codes[dtype], sh)
+            try:
+                d, z = pa.divergence_curl(M, uv)
+                d0 = pa.divergence(M, uv)
+                z0 = pa.curl(M, uv)
+                torch.cuda.synchronize()
+            finally:
+                pa.set_tune(M, pa.OP_DIVERGENCE, codes[dtype], None)
+            assert torch.equal(d + 0.0, d0 + 0.0), (L, sh)
+            assert torch.equal(z + 0.0, z0 + 0.0), (L, sh)
+    uv = torch.from_numpy(_input(32, 137, 2, 34)).to(DEV).to(dtype)
+    d = torch.empty((M.nnodes, 137), dtype=dtype, device=DEV)
+    with pytest.raises(pa.AtlasError):
+        pa.divergence_curl(M, uv, d, d)
