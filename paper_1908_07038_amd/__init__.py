@@ -444,5 +444,6 @@ def set_tune(mesh, op, dtype_code, shape=None):
         _check(lib().atlas_nabla_set_tune(mesh.handle, dtype_code, op, ctypes.byref(ts)))
 
 
-from .autograd import Gradient, Divergence, Laplacian, Curl, grad, div, lap, rot  # noqa: E402,F401
+from .autograd import (Gradient, Divergence, Laplacian, Curl, GradientLaplacian, DivergenceCurl,  # noqa: E402,F401
+                       grad, div, lap, rot, grad_lap, div_rot)
 from .batch import Batch  # noqa: E402,F401

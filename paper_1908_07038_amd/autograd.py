@@ -8,7 +8,8 @@ Laplacian L = D G has the adjoint G^T D^T.
 
 import torch
 
-from . import curl, curl_adjoint, divergence, divergence_adjoint, gradient, gradient_adjoint, laplacian
+from . import (curl, curl_adjoint, divergence, divergence_adjoint, divergence_curl, gradient, gradient_adjoint,
+               gradient_laplacian, laplacian)
 
 
 class Gradient(torch.autograd.Function):
@@ -55,6 +56,42 @@ class Curl(torch.autograd.Function):
         return None, curl_adjoint(ctx.mesh, zbar.contiguous())
 
 
+class GradientLaplacian(torch.autograd.Function):
+    """(grad f, lap f) in one pass; backward G^T (gbar + D^T lbar)."""
+
+    @staticmethod
+    def forward(ctx, mesh, f):
+        ctx.mesh = mesh
+        return gradient_laplacian(mesh, f.contiguous())
+
+    @staticmethod
+    def backward(ctx, gbar, lbar):
+        w = gbar.contiguous() if gbar is not None else None
+        if lbar is not None:
+            t = divergence_adjoint(ctx.mesh, lbar.contiguous())
+            w = t if w is None else w + t
+        return None, gradient_adjoint(ctx.mesh, w)
+
+
+class DivergenceCurl(torch.autograd.Function):
+    """(div uv, curl uv) in one pass; backward D^T dbar + C^T zbar."""
+
+    @staticmethod
+    def forward(ctx, mesh, uv):
+        ctx.mesh = mesh
+        return divergence_curl(mesh, uv.contiguous())
+
+    @staticmethod
+    def backward(ctx, dbar, zbar):
+        out = None
+        if dbar is not None:
+            out = divergence_adjoint(ctx.mesh, dbar.contiguous())
+        if zbar is not None:
+            t = curl_adjoint(ctx.mesh, zbar.contiguous())
+            out = t if out is None else out + t
+        return None, out
+
+
 def grad(mesh, f):
     return Gradient.apply(mesh, f)
 
@@ -70,3 +107,13 @@ def lap(mesh, f):
 def rot(mesh, uv):
     """Differentiable curl (vertical vorticity)."""
     return Curl.apply(mesh, uv)
+
+
+def grad_lap(mesh, f):
+    """Differentiable (gradient, Laplacian) of one field in one pass."""
+    return GradientLaplacian.apply(mesh, f)
+
+
+def div_rot(mesh, uv):
+    """Differentiable (divergence, curl) of one vector field in one pass."""
+    return DivergenceCurl.apply(mesh, uv)

@@ -223,6 +223,11 @@ def test_autograd_gradcheck():
     assert torch.autograd.gradcheck(lambda t: pa.div(M, t), (uv,), eps=1e-6, atol=1e-7)
     assert torch.autograd.gradcheck(lambda t: pa.lap(M, t), (f,), eps=1e-6, atol=1e-6)
     assert torch.autograd.gradcheck(lambda t: pa.rot(M, t), (uv,), eps=1e-6, atol=1e-7)
+    # the one-pass pairs: both outputs, and each alone (the other's cotangent absent)
+    assert torch.autograd.gradcheck(lambda t: pa.grad_lap(M, t), (f,), eps=1e-6, atol=1e-6)
+    assert torch.autograd.gradcheck(lambda t: pa.grad_lap(M, t)[1], (f,), eps=1e-6, atol=1e-6)
+    assert torch.autograd.gradcheck(lambda t: pa.div_rot(M, t), (uv,), eps=1e-6, atol=1e-7)
+    assert torch.autograd.gradcheck(lambda t: pa.div_rot(M, t)[0], (uv,), eps=1e-6, atol=1e-7)
 
 
 def test_curl_of_solid_body_rotation():
