@@ -103,6 +103,20 @@ def test_o1280_sampled_parity():
             del y
         del f, uv
         torch.cuda.empty_cache()
+    # the one-pass pairs equal the separate calls at full size, every dtype
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        f = f64.to(dt)
+        uv = uv64.to(dt)
+        g, lp = pa.gradient_laplacian(M, f)
+        assert torch.equal(g + 0.0, pa.gradient(M, f) + 0.0)
+        assert torch.equal(lp + 0.0, pa.laplacian(M, f) + 0.0)
+        del g, lp
+        d, z = pa.divergence_curl(M, uv)
+        assert torch.equal(d + 0.0, pa.divergence(M, uv) + 0.0)
+        assert torch.equal(z + 0.0, pa.curl(M, uv) + 0.0)
+        del d, z, f, uv
+        torch.cuda.empty_cache()
+    print("  one-pass pairs equal to the separate calls", flush=True)
     # invariants at full size
     f = f64.float()
     gc = pa.gradient(M, torch.full_like(f, 2.5))
