@@ -156,3 +156,16 @@ def apply(nodes, weights, f):
     for j in range(3):
         out += weights[:, j].reshape(shape) * f[nodes[:, j]]
     return out
+
+
+def apply_adjoint(nodes, weights, y, nnodes):
+    """Transpose of ``apply`` for the plain Euclidean inner product: the
+    value of target point t, weighted by w[t, j], is added to its node
+    nodes[t, j]; shape [nnodes, ...] with y's trailing axes."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.zeros((nnodes,) + y.shape[1:], dtype=np.float64)
+    shape = (-1,) + (1,) * (y.ndim - 1)
+    for j in range(3):
+        np.add.at(out, nodes[:, j], weights[:, j].reshape(shape) * y)
+    return out
+

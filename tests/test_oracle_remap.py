@@ -118,3 +118,20 @@ def test_locate_near_matches_locate():
     t1, n1, w1 = R.locate_near(xyz, tris, p, math.cos(0.5))
     np.testing.assert_array_equal(t0, t1)
     np.testing.assert_array_equal(w0, w1)
+
+
+def test_adjoint_is_the_dense_transpose():
+    # the interpolation as a dense P x V matrix, assembled entry by entry
+    xyz, tris = _src(6)
+    p = R.TargetGrid("F3").xyz
+    _, nodes, w = R.locate(xyz, tris, p)
+    A = np.zeros((p.shape[0], xyz.shape[0]))
+    for t in range(p.shape[0]):
+        for j in range(3):
+            A[t, nodes[t, j]] += w[t, j]
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((xyz.shape[0], 4))
+    y = rng.standard_normal((p.shape[0], 4))
+    np.testing.assert_allclose(R.apply(nodes, w, x), A @ x, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(R.apply_adjoint(nodes, w, y, xyz.shape[0]), A.T @ y, rtol=0, atol=1e-14)
+
