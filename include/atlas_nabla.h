@@ -227,7 +227,9 @@ typedef struct atlas_remap_s* atlas_remap_t;
 
 /* Locates every target point on the host (FP64) and, for a mesh built on a
  * device, uploads the tables (P x 16 bytes of node indices and P x 32 / 16
- * bytes of FP64 / FP32 weights).  The remap refers to `mesh`, which must
+ * bytes of FP64 / FP32 weights, and the transpose by source node: 8 bytes
+ * per node plus 3 x (4 + 8 + 4) bytes per point).  The remap refers to
+ * `mesh`, which must
  * outlive it.  *out owned by the caller; release with atlas_remap_free.
  * Statuses: ATLAS_EINVAL (NULL arguments, bad target name), ATLAS_ENOMEM,
  * ATLAS_ESHAPE (target too large), ATLAS_EHIP. */
@@ -250,6 +252,16 @@ int atlas_remap_export(atlas_remap_t remap, int32_t* nodes, double* weights, dou
  * ATLAS_BF16.  Asynchronous on `stream`. */
 int atlas_remap_apply(atlas_remap_t remap, int dtype, int32_t nlev, const void* src, void* dst,
                       void* stream);
+
+/* Exact transpose of atlas_remap_apply for the plain Euclidean inner
+ * product (sum(dst * ybar) == sum(src * fbar)): fbar[n][k] = the sum, over
+ * the target points t whose triangle has node n, in ascending t, of
+ * w_tn ybar[t][k] (fused multiply-adds; 0 for nodes no point uses).
+ * ybar: device [P][nlev]; fbar: device [V][nlev], overwritten, must not
+ * overlap ybar.  Weights as in atlas_remap_apply.  Asynchronous on
+ * `stream`. */
+int atlas_remap_apply_adjoint(atlas_remap_t remap, int dtype, int32_t nlev, const void* ybar, void* fbar,
+                              void* stream);
 
 /* ---- batched multi-tracer launch ------------------------------------------
  * Many fields with different level counts go through one persistent kernel

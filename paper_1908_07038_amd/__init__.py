@@ -103,6 +103,7 @@ _SIGS = {
     "atlas_remap_sizes": (ctypes.c_int, [_P, _I64P, _I64P]),
     "atlas_remap_export": (ctypes.c_int, [_P, _P, _P, _P]),
     "atlas_remap_apply": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
+    "atlas_remap_apply_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
 }
 
 
@@ -365,6 +366,22 @@ class Remap:
                                        ctypes.c_void_p(out.data_ptr()), _stream(f)))
         return out
 
+    def adjoint(self, ybar, out=None):
+        """[P][L] -> [V][L]: exact transpose of the remap."""
+        import torch
+        if (not ybar.is_cuda or ybar.dim() != 2 or ybar.shape[0] != self.npoints or not ybar.is_contiguous()):
+            raise ValueError("ybar must be a contiguous device tensor [npoints][nlev]")
+        nlev = ybar.shape[1]
+        if out is None:
+            out = torch.empty((self.mesh.nnodes, nlev), dtype=ybar.dtype, device=ybar.device)
+        else:
+            _field(self.mesh, out, 1, "out")
+            if out.dtype != ybar.dtype or out.shape[1] != nlev:
+                raise ValueError("out has the wrong dtype or shape")
+        _check(lib().atlas_remap_apply_adjoint(self._h, _dtype_code(ybar), nlev, ctypes.c_void_p(ybar.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream(ybar)))
+        return out
+
 
 def gradient_laplacian(mesh, f, out_grad=None, out_lap=None):
     """(gradient(f), laplacian(f)) in one pass over f (same values as the two
@@ -445,5 +462,5 @@ def set_tune(mesh, op, dtype_code, shape=None):
 
 
 from .autograd import (Gradient, Divergence, Laplacian, Curl, GradientLaplacian, DivergenceCurl,  # noqa: E402,F401
-                       grad, div, lap, rot, grad_lap, div_rot)
+                       RemapFunction, grad, div, lap, rot, grad_lap, div_rot, remap)
 from .batch import Batch  # noqa: E402,F401

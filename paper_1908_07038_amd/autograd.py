@@ -92,6 +92,19 @@ class DivergenceCurl(torch.autograd.Function):
         return None, out
 
 
+class RemapFunction(torch.autograd.Function):
+    """Remap of a node field (see Remap); backward the exact transpose."""
+
+    @staticmethod
+    def forward(ctx, r, f):
+        ctx.r = r
+        return r(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, ybar):
+        return None, ctx.r.adjoint(ybar.contiguous())
+
+
 def grad(mesh, f):
     return Gradient.apply(mesh, f)
 
@@ -117,3 +130,9 @@ def grad_lap(mesh, f):
 def div_rot(mesh, uv):
     """Differentiable (divergence, curl) of one vector field in one pass."""
     return DivergenceCurl.apply(mesh, uv)
+
+
+def remap(r, f):
+    """Differentiable remap of f [V][L] with the Remap r."""
+    return RemapFunction.apply(r, f)
+

@@ -678,10 +678,14 @@ struct atlas_remap_s {
   int32_t* nodes = nullptr;   // device [P][4]
   void* w64 = nullptr;        // device [P][4] FP64
   void* w32 = nullptr;        // device [P][4] FP32
+  int64_t* adj_off = nullptr; // device transpose by source node: [V+1]
+  int32_t* adj_t = nullptr;   // [3P]
+  void* adj_w64 = nullptr;    // [3P] FP64
+  void* adj_w32 = nullptr;    // [3P] FP32
   ~atlas_remap_s() {
     if (mesh && mesh->device >= 0) {
       DeviceGuard g(mesh->device);
-      for (void* p : {(void*)nodes, w64, w32})
+      for (void* p : {(void*)nodes, w64, w32, (void*)adj_off, (void*)adj_t, adj_w64, adj_w32})
         if (p) (void)hipFree(p);
     }
   }
@@ -720,6 +724,14 @@ int atlas_remap_build(atlas_mesh_t mesh, const char* target, atlas_remap_t* out)
                                reinterpret_cast<void**>(&r->nodes));
       if (e == hipSuccess) e = upload_to(r->host.w.data(), r->host.w.size() * sizeof(double), &r->w64);
       if (e == hipSuccess) e = upload_to(w32.data(), w32.size() * sizeof(float), &r->w32);
+      const std::vector<float> aw32 = to_f32(r->host.adj_w);
+      if (e == hipSuccess)
+        e = upload_to(r->host.adj_off.data(), r->host.adj_off.size() * sizeof(int64_t),
+                      reinterpret_cast<void**>(&r->adj_off));
+      if (e == hipSuccess)
+        e = upload_to(r->host.adj_t.data(), r->host.adj_t.size() * sizeof(int32_t), reinterpret_cast<void**>(&r->adj_t));
+      if (e == hipSuccess) e = upload_to(r->host.adj_w.data(), r->host.adj_w.size() * sizeof(double), &r->adj_w64);
+      if (e == hipSuccess) e = upload_to(aw32.data(), aw32.size() * sizeof(float), &r->adj_w32);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         delete r;
@@ -778,6 +790,27 @@ int atlas_remap_apply(atlas_remap_t remap, int dtype, int32_t nlev, const void* 
   const void* w = dtype == ATLAS_F64 ? remap->w64 : remap->w32;
   hipError_t e = launch_remap(dtype, remap->nodes, w, remap->host.P, nlev, src, dst, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "remap");
+  return ATLAS_OK;
+}
+
+int atlas_remap_apply_adjoint(atlas_remap_t remap, int dtype, int32_t nlev, const void* ybar, void* fbar,
+                              void* stream) {
+  if (!remap) return fail(ATLAS_EINVAL, "remap is NULL");
+  int rc = check_mesh_device(remap->mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  if ((rc = check_field(ybar, 1, es, "ybar"))) return rc;
+  if ((rc = check_field(fbar, 1, es, "fbar"))) return rc;
+  const size_t nin = (size_t)remap->host.P * nlev * es, nout = (size_t)remap->mesh->host.V * nlev * es;
+  if (overlaps(ybar, nin, fbar, nout)) return fail(ATLAS_EINVAL, "fbar overlaps ybar");
+  DeviceGuard g(remap->mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  const void* w = dtype == ATLAS_F64 ? remap->adj_w64 : remap->adj_w32;
+  hipError_t e = launch_remap_adjoint(dtype, remap->adj_off, remap->adj_t, w, remap->mesh->host.V, nlev, ybar, fbar,
+                                      (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "remap adjoint");
   return ATLAS_OK;
 }
 

@@ -1618,6 +1618,71 @@ hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nl
   else return launch_remap_tp<S, 4>(nodes, w, P, nlev, src, dst, st);
 }
 
+// Transpose of the remapping: fbar[n][k] = the sum over the entries (t, w)
+// of source node n, in ascending target order, of w ybar[t][k] (fused
+// multiply-adds from zero; 0 for nodes no target point uses).  Lanes over
+// levels as in k_remap, P lanes per node.
+template <class S, int U>
+__global__ __launch_bounds__(256) void k_remap_adj(const int64_t* __restrict__ off, const int32_t* __restrict__ tt,
+                                                   const void* __restrict__ wv, const S* __restrict__ in,
+                                                   S* __restrict__ out, int64_t V, int L, int lanes, int64_t nblocks,
+                                                   int remap) {
+  using C = typename Traits<S>::C;
+  const C* __restrict__ w = static_cast<const C*>(wv);
+  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
+  if (lb >= nblocks) return;
+  const int W = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int G = 64 / lanes;
+  const int j = lane / lanes, tl = lane - j * lanes;
+  if (j >= G) return;   // idle lanes; the kernel has no barrier
+  const int64_t n = (lb * W + wave) * G + j;
+  if (n >= V) return;
+  const int64_t e0 = off[n], e1 = off[n + 1];
+  S* __restrict__ o = out + (size_t)n * (size_t)L;
+  for (int k0 = tl; k0 < L; k0 += lanes * U) {
+    C acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const S* __restrict__ src = in + (size_t)tt[e] * (size_t)L;
+      const C we = w[e];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + lanes * u;
+        acc[u] = fma(we, ld1(src + (k < L ? k : L - 1)), acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + lanes * u;
+      if (k < L) st1<false>(o + k, acc[u]);
+    }
+  }
+}
+
+template <class S>
+hipError_t launch_remap_adj_t(const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
+                              const void* in, void* out, hipStream_t st) {
+  const int lanes = nlev <= 32 ? nlev : 64;
+  const int G = 64 / lanes;
+  constexpr int W = 4;
+  const int64_t groups = (V + G - 1) / G;
+  const int64_t nblocks = (groups + W - 1) / W;
+  const int64_t grid = (nblocks + 7) / 8 * 8;
+  const int nsl = (nlev + lanes - 1) / lanes;
+  const int U = nsl < 3 ? nsl : 3;
+  const dim3 g((unsigned)grid), b(64 * W);
+  const S* src = static_cast<const S*>(in);
+  S* dst = static_cast<S*>(out);
+  switch (U) {
+    case 1: hipLaunchKernelGGL((k_remap_adj<S, 1>), g, b, 0, st, off, tt, w, src, dst, V, nlev, lanes, nblocks, 1); break;
+    case 2: hipLaunchKernelGGL((k_remap_adj<S, 2>), g, b, 0, st, off, tt, w, src, dst, V, nlev, lanes, nblocks, 1); break;
+    default: hipLaunchKernelGGL((k_remap_adj<S, 3>), g, b, 0, st, off, tt, w, src, dst, V, nlev, lanes, nblocks, 1); break;
+  }
+  return hipGetLastError();
+}
+
 // ---- conservation: fixed-order FP64 sums of V_i div_ik --------------------------
 //
 // Workgroup b reduces nodes [b*chunk, (b+1)*chunk) for every level.  Wave w
@@ -2275,6 +2340,17 @@ hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t 
     case DT_F64: return launch_remap_t<double>(nodes, w, P, nlev, in, out, stream);
     case DT_F32: return launch_remap_t<float>(nodes, w, P, nlev, in, out, stream);
     case DT_BF16: return launch_remap_t<bf16_t>(nodes, w, P, nlev, in, out, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
+                                const void* in, void* out, hipStream_t stream) {
+  if (V < 1 || nlev < 1 || (V + 15) / 16 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  switch (dtype) {
+    case DT_F64: return launch_remap_adj_t<double>(off, tt, w, V, nlev, in, out, stream);
+    case DT_F32: return launch_remap_adj_t<float>(off, tt, w, V, nlev, in, out, stream);
+    case DT_BF16: return launch_remap_adj_t<bf16_t>(off, tt, w, V, nlev, in, out, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -144,6 +144,10 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
 // fourth entries unused.
 hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
                         void* out, hipStream_t stream);
+// Its transpose: out[n][k] = sum over e in [off[n], off[n+1]) of w[e] in[tt[e]][k]
+// for the V source nodes (off [V+1] int64, tt int32, w of the weight type).
+hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
+                                const void* in, void* out, hipStream_t stream);
 
 // Batched persistent launch over a device table of work items.
 struct BatchItem {

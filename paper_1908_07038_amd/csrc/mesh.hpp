@@ -141,6 +141,12 @@ struct RemapHost {
   std::vector<int32_t> nodes;     // [P][4]: three source nodes, 0 padding
   std::vector<double> w;          // [P][4]: their weights, 0 padding
   int64_t fallback = 0;           // points located by the exhaustive search
+  // transpose (adjoint) in compressed rows by source node: the entries
+  // (target point, weight) of node n are adj_t/adj_w[adj_off[n] .. adj_off[n+1]),
+  // in ascending target order
+  std::vector<int64_t> adj_off;   // [V+1]
+  std::vector<int32_t> adj_t;     // [3P]
+  std::vector<double> adj_w;      // [3P]
 };
 
 // Parse "F<M>" or "O<M>"; returns M (kind in *kind) or -1.

@@ -187,6 +187,20 @@ void build_remap(const HostMesh& m, const std::string& target, RemapHost& out) {
     out.w[4 * g + 1] = db / d;
     out.w[4 * g + 2] = dc / d;
   }
+  // transpose by source node (counting sort; targets stay ascending)
+  out.adj_off.assign(m.V + 1, 0);
+  for (int64_t g = 0; g < P; ++g)
+    for (int s = 0; s < 3; ++s) ++out.adj_off[out.nodes[4 * g + s] + 1];
+  for (int64_t i = 0; i < m.V; ++i) out.adj_off[i + 1] += out.adj_off[i];
+  out.adj_t.resize(3 * P);
+  out.adj_w.resize(3 * P);
+  std::vector<int64_t> fill(out.adj_off.begin(), out.adj_off.end() - 1);
+  for (int64_t g = 0; g < P; ++g)
+    for (int s = 0; s < 3; ++s) {
+      const int64_t e = fill[out.nodes[4 * g + s]]++;
+      out.adj_t[e] = (int32_t)g;
+      out.adj_w[e] = out.w[4 * g + s];
+    }
 }
 
 }  // namespace atlasnabla

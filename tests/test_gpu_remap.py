@@ -110,3 +110,33 @@ def test_remap_argument_errors():
     with pytest.raises(pa.AtlasError) as e:
         r(big[:M.nnodes], out=big[M.nnodes - 1:M.nnodes - 1 + r.npoints])
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+@pytest.mark.parametrize("L", [1, 10, 65, 137])
+@pytest.mark.parametrize("src,dst", [("O32", "F8"), ("O12", "F30"), ("O24", "F24")])
+def test_remap_adjoint_parity(src, dst, L, dtype):
+    """The transpose kernel against the oracle's scatter, and (FP64) the
+    dot-product identity <R x, y> = <x, R^T y>."""
+    print(f"case remap adjoint {src}->{dst} L {L} {dtype}", flush=True)
+    r = gpu_remap(src, dst)
+    y = torch.from_numpy(np.random.default_rng(7 + L).standard_normal((r.npoints, L))).to(DEV).to(dtype)
+    fb = r.adjoint(y)
+    torch.cuda.synchronize()
+    nodes, w = oracle_remap(src, dst)
+    ref = R.apply_adjoint(nodes, w, y.double().cpu().numpy(), r.mesh.nnodes)
+    err = rel(fb.double().cpu().numpy(), ref)
+    assert err <= TOL[dtype], (src, dst, L, dtype, err)
+    if dtype == torch.float64:
+        x = torch.from_numpy(_input(int(src[1:]), L, 60 + L)).to(DEV)
+        rx = r(x)
+        lhs = float((rx * y).sum())
+        rhs = float((x * fb).sum())
+        assert abs(lhs - rhs) <= 1e-13 * float(rx.norm() * y.norm()), (lhs, rhs)
+
+
+def test_remap_autograd_gradcheck():
+    M = gpu_mesh(4)
+    r = pa.Remap(M, "F2")
+    f = torch.from_numpy(np.random.default_rng(3).standard_normal((M.nnodes, 3))).to(DEV).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: pa.remap(r, t), (f,), eps=1e-6, atol=1e-8)
