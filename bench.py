@@ -259,8 +259,22 @@ def run_remap(args, pa, mesh, f64):
         out[dname] = {"ms": round(ms, 4), "alg_GB": round(by / 1e9, 3), "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
                       "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3),
                       "point_levels_s": float(f"{P * L / (ms * 1e-3):.4g}")}
-        log(f"remap {dname}: {ms:.3f} ms, {out[dname]['GB_s']:.0f} GB/s algorithmic")
-        del x, y
+        # the transpose (target field -> source nodes): reads the target
+        # columns once, writes every source column, plus its tables
+        fb = torch.empty((V, L), dtype=dtype, device=x.device)
+        r.adjoint(y, out=fb)
+        a.record()
+        for _ in range(args.steps):
+            r.adjoint(y, out=fb)
+        b.record()
+        torch.cuda.synchronize()
+        ms_t = a.elapsed_time(b) / args.steps
+        by_t = (P + V) * L * esize + 8 * V + 3 * P * (4 + (8 if dname == "f64" else 4))
+        out[dname]["adjoint"] = {"ms": round(ms_t, 4), "GB_s": round(by_t / (ms_t * 1e-3) / 1e9, 1),
+                                 "hbm_frac": round(by_t / (ms_t * 1e-3) / HBM_PEAK, 3)}
+        log(f"remap {dname}: {ms:.3f} ms, {out[dname]['GB_s']:.0f} GB/s algorithmic; "
+            f"adjoint {ms_t:.3f} ms, {out[dname]['adjoint']['GB_s']:.0f} GB/s")
+        del x, y, fb
     r.close()
     return out
 
