@@ -397,7 +397,7 @@ def main():
                     help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has no "
               "multi-GPU path (levels and tracers would shard with no communication). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
