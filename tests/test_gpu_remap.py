@@ -55,7 +55,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-CASES = [("O32", "F8"), ("O16", "O16"), ("O12", "F30"), ("O24", "F24"), ("O20", "O9")]
+CASES = [("O32", "F8"), ("O16", "O16"), ("O12", "F30"), ("O24", "F24"), ("O20", "O9"), ("O1", "F6")]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])

@@ -11,7 +11,8 @@ from oracle import remap as R
 
 
 @pytest.mark.parametrize("src,dst", [("O32", "F8"), ("O16", "O16"), ("O12", "F30"), ("O8", "O3"),
-                                     ("O24", "F24"), ("O4", "F1"), ("O20", "O9")])
+                                     ("O24", "F24"), ("O4", "F1"), ("O20", "O9"), ("O1", "F1"), ("O1", "O1"),
+                                     ("O2", "F40")])
 def test_remap_tables_match_the_oracle(src, dst):
     """Target positions equal the oracle's; every chosen triangle is a mesh
     triangle containing the point; interpolated values agree with the
