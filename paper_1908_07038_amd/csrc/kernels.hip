@@ -1621,7 +1621,7 @@ hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nl
 // Transpose of the remapping: fbar[n][k] = the sum over the entries (t, w)
 // of source node n, in ascending target order, of w ybar[t][k] (fused
 // multiply-adds from zero; 0 for nodes no target point uses).  Lanes over
-// levels as in k_remap, P lanes per node.
+// levels as in k_remap, P lanes per node (64 / P nodes per wave).
 template <class S, int U>
 __global__ __launch_bounds__(256) void k_remap_adj(const int64_t* __restrict__ off, const int32_t* __restrict__ tt,
                                                    const void* __restrict__ wv, const S* __restrict__ in,
@@ -1664,7 +1664,9 @@ __global__ __launch_bounds__(256) void k_remap_adj(const int64_t* __restrict__ o
 template <class S>
 hipError_t launch_remap_adj_t(const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
                               const void* in, void* out, hipStream_t st) {
-  const int lanes = nlev <= 32 ? nlev : 64;
+  // 4- and 2-byte data: 16 lanes per node, four nodes' dependent row, index
+  // and data loads in flight per wave (measured at O1280 x 137 <- F640)
+  const int lanes = sizeof(S) == 8 ? (nlev <= 32 ? nlev : 64) : (nlev <= 16 ? nlev : 16);
   const int G = 64 / lanes;
   constexpr int W = 4;
   const int64_t groups = (V + G - 1) / G;
