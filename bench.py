@@ -58,8 +58,10 @@ def kernel_names(pa, mesh, dtype_code, L):
     # the one-pass gradient and Laplacian runs the Laplacian's one-tile shape
     # with kernel operator 7; on any other shape it is the two calls
     lap = names["laplacian"]
-    names["gradient_laplacian"] = (lap.replace(", 4, ", ", 7, ") if lap.startswith("k_tile<")
-                                   else names["gradient"] + " + " + lap)
+    fused = lap.replace(", 4, ", ", 7, ")
+    if dtype_code == pa.F64 and fused.startswith("k_tile<"):   # one slice per step in FP64
+        fused = fused[:fused.rindex(",")] + ", 1>"
+    names["gradient_laplacian"] = fused if lap.startswith("k_tile<") else names["gradient"] + " + " + lap
     return names
 
 
