@@ -254,6 +254,16 @@ def _field(mesh, t, comps, name):
     return t.shape[1]
 
 
+def _like(mesh, t, comps, nlev, dtype, name):
+    """Checks a caller-given output or workspace: a contiguous device tensor
+    [nnodes][nlev] (or [nnodes][nlev][2]) of the input's dtype.  The kernels
+    write nnodes * nlev (* 2) elements through it, so a smaller or narrower
+    buffer is refused here."""
+    if _field(mesh, t, comps, name) != nlev or t.dtype != dtype:
+        raise ValueError(f"{name} must be [nnodes][{nlev}]" + ("[2]" if comps == 2 else "") + f" of {dtype}")
+    return t
+
+
 def _apply(fn, mesh, x, in_comps, out_comps, out):
     import torch
     nlev = _field(mesh, x, in_comps, "input")
@@ -261,9 +271,7 @@ def _apply(fn, mesh, x, in_comps, out_comps, out):
     if out is None:
         out = torch.empty(shape, dtype=x.dtype, device=x.device)
     else:
-        _field(mesh, out, out_comps, "out")
-        if out.dtype != x.dtype or tuple(out.shape) != shape:
-            raise ValueError("out has the wrong dtype or shape")
+        _like(mesh, out, out_comps, nlev, x.dtype, "out")
     _check(fn(mesh.handle, _dtype_code(x), nlev, ctypes.c_void_p(x.data_ptr()),
               ctypes.c_void_p(out.data_ptr()), _stream(x)))
     return out
@@ -304,11 +312,13 @@ def laplacian(mesh, f, out=None, workspace=None):
     ([V][L][2], same dtype) when given."""
     import torch
     nlev = _field(mesh, f, 1, "f")
+    if workspace is not None:
+        _like(mesh, workspace, 2, nlev, f.dtype, "workspace")
     if out is None:
         out = torch.empty_like(f)
+    else:
+        _like(mesh, out, 1, nlev, f.dtype, "out")
     ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
-    if workspace is not None:
-        _field(mesh, workspace, 2, "workspace")
     _check(lib().atlas_nabla_laplacian(mesh.handle, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), ws, _stream(f)))
     return out
@@ -375,9 +385,7 @@ class Remap:
         if out is None:
             out = torch.empty((self.mesh.nnodes, nlev), dtype=ybar.dtype, device=ybar.device)
         else:
-            _field(self.mesh, out, 1, "out")
-            if out.dtype != ybar.dtype or out.shape[1] != nlev:
-                raise ValueError("out has the wrong dtype or shape")
+            _like(self.mesh, out, 1, nlev, ybar.dtype, "out")
         _check(lib().atlas_remap_apply_adjoint(self._h, _dtype_code(ybar), nlev, ctypes.c_void_p(ybar.data_ptr()),
                                                ctypes.c_void_p(out.data_ptr()), _stream(ybar)))
         return out
@@ -388,14 +396,14 @@ def gradient_laplacian(mesh, f, out_grad=None, out_lap=None):
     calls, up to the sign of zero)."""
     import torch
     nlev = _field(mesh, f, 1, "f")
+    if out_grad is not None:
+        _like(mesh, out_grad, 2, nlev, f.dtype, "out_grad")
+    if out_lap is not None:
+        _like(mesh, out_lap, 1, nlev, f.dtype, "out_lap")
     if out_grad is None:
         out_grad = torch.empty((mesh.nnodes, nlev, 2), dtype=f.dtype, device=f.device)
     if out_lap is None:
         out_lap = torch.empty_like(f)
-    _field(mesh, out_grad, 2, "out_grad")
-    _field(mesh, out_lap, 1, "out_lap")
-    if out_grad.dtype != f.dtype or out_lap.dtype != f.dtype or out_grad.shape[1] != nlev or out_lap.shape[1] != nlev:
-        raise ValueError("outputs have the wrong dtype or shape")
     _check(lib().atlas_nabla_gradient_laplacian(mesh.handle, _dtype_code(f), nlev, ctypes.c_void_p(f.data_ptr()),
                                                 ctypes.c_void_p(out_grad.data_ptr()),
                                                 ctypes.c_void_p(out_lap.data_ptr()), _stream(f)))
@@ -407,14 +415,14 @@ def divergence_curl(mesh, uv, out_div=None, out_curl=None):
     calls, up to the sign of zero)."""
     import torch
     nlev = _field(mesh, uv, 2, "uv")
+    if out_div is not None:
+        _like(mesh, out_div, 1, nlev, uv.dtype, "out_div")
+    if out_curl is not None:
+        _like(mesh, out_curl, 1, nlev, uv.dtype, "out_curl")
     if out_div is None:
         out_div = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
     if out_curl is None:
         out_curl = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
-    _field(mesh, out_div, 1, "out_div")
-    _field(mesh, out_curl, 1, "out_curl")
-    if out_div.dtype != uv.dtype or out_curl.dtype != uv.dtype or out_div.shape[1] != nlev or out_curl.shape[1] != nlev:
-        raise ValueError("outputs have the wrong dtype or shape")
     _check(lib().atlas_nabla_divergence_curl(mesh.handle, _dtype_code(uv), nlev, ctypes.c_void_p(uv.data_ptr()),
                                              ctypes.c_void_p(out_div.data_ptr()),
                                              ctypes.c_void_p(out_curl.data_ptr()), _stream(uv)))

@@ -4,7 +4,7 @@ fields with different level counts, optionally replayed as a HIP graph."""
 import ctypes
 
 from . import (F32, F64, OP_DIVERGENCE, OP_DIVERGENCE_ADJOINT, OP_GRADIENT, OP_GRADIENT_ADJOINT,
-               TracerDesc, TuneShape, _check, _dtype_code, _stream, lib)
+               TracerDesc, TuneShape, _check, _dtype_code, _field, _like, _stream, lib)
 
 _OPS = {"gradient": OP_GRADIENT, "divergence": OP_DIVERGENCE,
         "gradient_adjoint": OP_GRADIENT_ADJOINT, "divergence_adjoint": OP_DIVERGENCE_ADJOINT}
@@ -33,35 +33,35 @@ class Batch:
         self.mesh = mesh
         self.mask = mask
         self._keep = []
-        descs = (TracerDesc * len(tracers))()
         dtype = None
+        levels = []
         for t, tr in enumerate(tracers):
             if set(tr) != names:
                 raise ValueError("all tracers must use the same operators")
             nlev = None
             for n, (x, y) in tr.items():
-                op = _OPS[n]
-                ci, co = _COMPS[op]
-                if x.shape[0] != mesh.nnodes or y.shape[0] != mesh.nnodes:
-                    raise ValueError("fields must be [nnodes][nlev](, 2)")
-                if (x.dim() != (3 if ci == 2 else 2)) or (y.dim() != (3 if co == 2 else 2)):
-                    raise ValueError(f"tracer {t} {n}: wrong field rank")
-                if not (x.is_contiguous() and y.is_contiguous()) or x.dtype != y.dtype:
-                    raise ValueError(f"tracer {t} {n}: fields must be contiguous and of one dtype")
-                if nlev is None:
-                    nlev = x.shape[1]
-                if x.shape[1] != nlev or y.shape[1] != nlev:
+                ci, co = _COMPS[_OPS[n]]
+                # contiguous device tensors [nnodes][nlev], or [nnodes][nlev][2]
+                # for vector fields, one level count per tracer
+                lx = _field(mesh, x, ci, f"tracer {t} {n} input")
+                nlev = lx if nlev is None else nlev
+                _like(mesh, y, co, nlev, x.dtype, f"tracer {t} {n} output")
+                if lx != nlev:
                     raise ValueError(f"tracer {t}: all fields need the same level count")
                 dtype = _dtype_code(x) if dtype is None else dtype
                 if _dtype_code(x) != dtype:
                     raise ValueError("one dtype per plan")
-                b = _BIT[op]
+            levels.append(nlev)
+        if dtype not in (F32, F64):
+            raise ValueError("batched plans take float32 or float64 fields")
+        descs = (TracerDesc * len(tracers))()
+        for t, tr in enumerate(tracers):
+            descs[t].nlev = levels[t]
+            for n, (x, y) in tr.items():
+                b = _BIT[_OPS[n]]
                 descs[t].in_[b] = x.data_ptr()
                 descs[t].out[b] = y.data_ptr()
                 self._keep += [x, y]
-            descs[t].nlev = nlev
-        if dtype not in (F32, F64):
-            raise ValueError("batched plans take float32 or float64 fields")
         self.dtype = dtype
         self.device_tensor = tracers[0][next(iter(names))][0]
         ts = TuneShape(**tune) if tune else None

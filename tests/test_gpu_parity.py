@@ -1,12 +1,19 @@
 """GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle.
 
-Bars (normwise relative L2, ||gpu - oracle|| / ||oracle||):
+Bars: normwise relative L2 ||gpu - oracle|| / ||oracle|| and element-wise
+max |gpu - oracle| / max |oracle|, both under the tolerance, the element-wise
+one also per level and on the polar rows and the nodes of degree 5 and 7
+separately (tests/_parity.py):
   FP64: <= 1e-12.
-  FP32: <= 1e-5 against the oracle applied to the FP64 input (total error).
+  FP32: <= 1e-5 against the oracle applied to the FP32-rounded input (the
+    kernel's own error), and <= 1e-5 normwise against the oracle applied to
+    the FP64 input (total error, the input rounding included: a Laplacian of
+    a field with a large level offset amplifies that rounding to ~1e-5 at
+    single nodes, so the total error is bounded normwise only).
   BF16 storage: <= 4e-3 against the oracle applied to the bf16-rounded input
-    (each output is rounded once to bfloat16, whose half-ulp is 2^-8 of the
-    value; FP32 arithmetic adds ~1e-6).  The total error against the FP64
-    input is printed, not bounded here.
+    (each output is rounded once to bfloat16, whose half-ulp is at most 2^-8
+    of the value; FP32 arithmetic adds ~1e-6).  The total error against the
+    FP64 input is printed, not bounded here.
 Sizes span several workgroups, ragged level tails (nlev not a multiple of 64)
 and every launch form: several nodes per wave (nlev <= 32) and one node per
 wave (nlev > 32).
@@ -19,6 +26,7 @@ import paper_1908_07038_amd as pa
 import workloads as W
 from oracle import nabla
 from _oracle_cache import mesh_and_dual, coords
+from _parity import check, special_groups
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +75,7 @@ def _run(name, N, L, dtype, seed=11):
     xt = torch.from_numpy(x).to(DEV).to(dtype)
     y = gpu_fn(gpu_mesh(N), xt)
     torch.cuda.synchronize()
-    xin = xt.double().cpu().numpy() if dtype == torch.bfloat16 else x
+    xin = xt.double().cpu().numpy() if dtype != torch.float64 else x
     ref = ora_fn(m, g, xin)
     return y.double().cpu().numpy(), ref, x, m, g
 
@@ -81,11 +89,13 @@ CASES = [(4, 1), (4, 3), (32, 10), (32, 19), (32, 33), (32, 64), (32, 137), (1, 
 def test_parity(name, N, L, dtype):
     print(f"case {name} O{N} x {L} {dtype}", flush=True)
     y, ref, x, m, g = _run(name, N, L, dtype)
-    err = rel(y, ref)
-    assert err <= TOL[dtype], (name, N, L, dtype, err)
-    if dtype == torch.bfloat16:
+    err, emax = check(y, ref, TOL[dtype], (name, N, L, str(dtype)), per_level=True, groups=special_groups(m))
+    print(f"  rel L2 {err:.2e} max {emax:.2e}")
+    if dtype != torch.float64:
         total = rel(y, OPS[name][2](m, g, x))
-        print(f"  bf16 kernel-only {err:.2e} total {total:.2e}")
+        print(f"  kernel-only {err:.2e} total {total:.2e}")
+        if dtype == torch.float32:
+            assert total <= TOL[dtype], (name, N, L, "total", total)
 
 
 TILE_CODES = {torch.float64: pa.F64, torch.float32: pa.F32}
@@ -108,11 +118,10 @@ def test_parity_lds_tiles(name, N, L, kb, form, dtype):
     M = gpu_mesh(N)
     pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], dict(lds_tiles=form, tile_kb=kb))
     try:
-        y, ref, _, _, _ = _run(name, N, L, dtype)
+        y, ref, _, m, _ = _run(name, N, L, dtype)
     finally:
         pa.set_tune(M, OP_BITS[name], TILE_CODES[dtype], None)
-    err = rel(y, ref)
-    assert err <= TOL[dtype], (name, N, L, dtype, err)
+    check(y, ref, TOL[dtype], (name, N, L, kb, form, str(dtype)), per_level=True, groups=special_groups(m))
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -129,8 +138,13 @@ def test_config_o32(dtype):
     og = nabla.gradient(m, g, f)
     od = nabla.divergence(m, g, og)
     ol = nabla.laplacian(m, g, f)
-    for y, r in [(gr, og), (dv, od), (lp, ol)]:
-        assert rel(y.double().cpu().numpy(), r) <= TOL[dtype]
+    fk = ft.double().cpu().numpy()                 # the input as the kernel sees it
+    ogk = nabla.gradient(m, g, fk)
+    kern = {"gradient": ogk, "divergence": nabla.divergence(m, g, ogk), "laplacian": nabla.laplacian(m, g, fk)}
+    for what, y, r in [("gradient", gr, og), ("divergence", dv, od), ("laplacian", lp, ol)]:
+        yy = y.double().cpu().numpy()
+        check(yy, kern[what], TOL[dtype], what, per_level=True, groups=special_groups(m))
+        assert rel(yy, r) <= TOL[dtype], (what, "total", rel(yy, r))
     # the fused and two-pass Laplacian agree with div(grad f) computed on the GPU
     np.testing.assert_allclose(lp.double().cpu().numpy(), dv.double().cpu().numpy(),
                                rtol=0, atol=TOL[dtype] * np.abs(ol).max() * 10)
@@ -147,7 +161,10 @@ def test_two_pass_laplacian(dtype):
     gr = pa.gradient(M, ft)
     torch.cuda.synchronize()
     assert torch.equal(ws, gr)               # the workspace holds the gradient
-    assert rel(l2.double().cpu().numpy(), nabla.laplacian(m, g, f)) <= TOL[dtype]
+    yy = l2.double().cpu().numpy()
+    check(yy, nabla.laplacian(m, g, ft.double().cpu().numpy()), TOL[dtype], "two-pass laplacian",
+          per_level=True, groups=special_groups(m))
+    assert rel(yy, nabla.laplacian(m, g, f)) <= TOL[dtype]
 
 
 def test_conservation_sums():
@@ -258,6 +275,13 @@ def test_argument_errors():
     assert L.atlas_nabla_gradient(M.handle, 1, 4, g.data_ptr(), g.data_ptr(), None) == -1   # overlap
     with pytest.raises(ValueError):
         pa.gradient(M, g)
+    # caller-given outputs and workspaces must match the input
+    with pytest.raises(ValueError):
+        pa.laplacian(M, f, out=torch.empty((M.nnodes, 4), dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        pa.laplacian(M, f, workspace=torch.empty((M.nnodes, 3, 2), dtype=torch.float32, device=DEV))
+    with pytest.raises(ValueError):
+        pa.gradient(M, f, out=torch.empty((M.nnodes, 4, 3), dtype=torch.float32, device=DEV))
     torch.cuda.synchronize()
 
 
