@@ -213,6 +213,24 @@ int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev,
                              const void* div, double* out_sum, double* out_abs,
                              void* stream);
 
+/* atlas_nabla_conservation for callers that cannot allocate device memory
+ * (code under stream capture into a graph, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and the same results, bit for bit,
+ * with the partial sums in a 16 MiB array the library holds on each GPU
+ * until the process ends, instead of a buffer allocated on first use.  It
+ * makes no hipMalloc, hipFree or other allocating call.  The caller passes
+ * div, out_sum and out_abs as for atlas_nabla_conservation.  Limit: the
+ * partial sums, min(4096, ceil(V / 64)) x nlev x 16 bytes, must fit the
+ * array (at most 256 levels on meshes of 262,144 nodes or more, e.g. O320 to
+ * O1280); larger nlev returns ATLAS_ESHAPE with the limit in the message.
+ * Every entry of the array a call reads is written earlier in that call, so
+ * nothing needs clearing; but all calls on one GPU share the array, so
+ * calls that overlap in time on that GPU (different streams, or threads)
+ * race and must be serialised by the caller. */
+int atlas_nabla_conservation_noalloc(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                     const void* div, double* out_sum, double* out_abs,
+                                     void* stream);
+
 /* ---- grid-to-grid remapping (Section 4.3, Figures 4-6) ----------------------
  * A field on the nodes of an O-grid mesh is interpolated to the points of a
  * target grid, linearly over the source triangle each point lies in, in 3-D

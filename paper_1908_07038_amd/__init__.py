@@ -82,6 +82,7 @@ _SIGS = {
     "atlas_nabla_gradient_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_divergence_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_conservation": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_conservation_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_gradient_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_divergence_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
@@ -439,6 +440,23 @@ def conservation(mesh, div):
                                           ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(a.data_ptr()),
                                           _stream(div)))
     return s, a
+
+
+def conservation_noalloc(mesh, div, out_sum, out_abs):
+    """conservation() into caller-given FP64 [nlev] device tensors; the library
+    allocates nothing (its partial sums live in a static per-GPU array, so
+    calls that overlap on one GPU race)."""
+    import torch
+    nlev = _field(mesh, div, 1, "div")
+    for t, name in ((out_sum, "out_sum"), (out_abs, "out_abs")):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == div.device
+                and tuple(t.shape) == (nlev,) and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({nlev},) on {div.device}")
+    _check(lib().atlas_nabla_conservation_noalloc(mesh.handle, _dtype_code(div), nlev,
+                                                  ctypes.c_void_p(div.data_ptr()),
+                                                  ctypes.c_void_p(out_sum.data_ptr()),
+                                                  ctypes.c_void_p(out_abs.data_ptr()), _stream(div)))
+    return out_sum, out_abs
 
 
 def tune(mesh, op, x, out, reps=10):

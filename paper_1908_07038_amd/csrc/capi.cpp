@@ -660,6 +660,36 @@ int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev, const v
   return ATLAS_OK;
 }
 
+int atlas_nabla_conservation_noalloc(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* div, double* out_sum,
+                                     double* out_abs, void* stream) {
+  int rc = check_mesh_device(mesh);
+  if (rc) return rc;
+  const size_t es = dtype_size(dtype);
+  if (!es) return fail(ATLAS_EDTYPE, "unknown dtype " + std::to_string(dtype));
+  if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
+  if ((rc = check_field(div, 1, es, "div"))) return rc;
+  if ((rc = check_field(out_sum, 1, 8, "out_sum"))) return rc;
+  if ((rc = check_field(out_abs, 1, 8, "out_abs"))) return rc;
+  if (overlaps(out_sum, 8 * (size_t)nlev, out_abs, 8 * (size_t)nlev))
+    return fail(ATLAS_EINVAL, "out_sum overlaps out_abs");
+  const int64_t V = mesh->host.V;
+  const size_t need = (size_t)conservation_parts(V, nlev) * (size_t)nlev * 2 * sizeof(double);
+  if (need > kScratchBytes)
+    return fail(ATLAS_ESHAPE, "nlev " + std::to_string(nlev) + " needs " + std::to_string(need) +
+                                  " bytes of partial sums, more than the " + std::to_string(kScratchBytes) +
+                                  "-byte static buffer (at most " +
+                                  std::to_string(kScratchBytes / ((size_t)conservation_parts(V, 1) * 16)) +
+                                  " levels on this mesh)");
+  DeviceGuard g(mesh->device);
+  if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
+  double* part = nullptr;
+  hipError_t e = scratch_address(mesh->device, &part);
+  if (e != hipSuccess) return hip_fail(e, "conservation_noalloc: scratch address");
+  e = launch_conservation(dtype, mesh->vol, V, nlev, div, part, out_sum, out_abs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "conservation_noalloc");
+  return ATLAS_OK;
+}
+
 int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op, const atlas_tune_t* tune) {
   if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
   if (!dtype_size(dtype)) return fail(ATLAS_EDTYPE, "unknown dtype");

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <mutex>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -2318,6 +2319,31 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cons_final, dim3(nlev), dim3(256), 0, stream, scratch, parts, nlev, out_sum, out_abs);
   return hipGetLastError();
+}
+
+// Partial sums of the allocation-free conservation call: one array per GPU,
+// held by the library until the process ends.  In host code `scratch` names
+// a host-side stand-in, never the device memory: kernels and copies take the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, double** ptr) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    // the caller has made `device` current
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape) {

@@ -139,6 +139,14 @@ hipError_t launch_conservation(int dtype, const double* vol, int64_t V, int nlev
                                const void* div, double* scratch, double* out_sum,
                                double* out_abs, hipStream_t stream);
 
+// Device array for the allocation-free conservation call's partial sums
+// (conservation_parts(V, nlev) * nlev * 2 doubles must fit), one per GPU.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int kMaxScratchDevices = 64;
+// Its device address on `device`, which must be the current device; looked
+// up on the first call per device, then cached.
+hipError_t scratch_address(int device, double** ptr);
+
 // Remapping: out[t][k] = sum_j w[t][j] in[nodes[t][j]][k] over P target
 // points; nodes [P][4] int32 and w [P][4] (FP64 for DT_F64, FP32 otherwise),
 // fourth entries unused.
