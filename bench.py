@@ -98,6 +98,24 @@ def measured_traffic(op, dtype_name):
     return None
 
 
+def sample_nodes(mesh, count, seed):
+    """Nodes where the outputs are checked against the FP64 oracle (sorted
+    unique): the two polar rows at each pole, every node of degree 5 or 7,
+    row starts, a run of the equatorial row and `count` random nodes, from
+    the mesh's exported grid and connectivity."""
+    import numpy as np
+
+    gr = mesh.export_grid()
+    deg = np.diff(mesh.export_connectivity()["csr_off"])
+    ro, rs = gr["row_off"], gr["row_size"]
+    R = rs.size
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([
+        np.arange(ro[0], ro[2]), np.arange(ro[R - 2], ro[R]), np.nonzero(deg != 6)[0],
+        ro[:-1][::max(1, R // 64)], ro[R // 2 - 1] + np.arange(0, rs[R // 2 - 1], 97),
+        rng.choice(mesh.nnodes, count, replace=False)])).astype(np.int64)
+
+
 def run_gpu(args):
     import torch
 
@@ -113,12 +131,15 @@ def run_gpu(args):
     t0 = time.time()
     s, trend = W.workload_o1280(mesh.coords(), nlev=L, device=dev)
     f64 = (s[:, None] + torch.from_numpy(trend).to(dev)[None, :]).contiguous()
-    del s
     torch.cuda.synchronize()
     log(f"input generated in {time.time() - t0:.1f}s")
 
     results = {}
-    refs = {}
+    # sample nodes for the error against the FP64 oracle, and the input rows
+    # on their three-ring (what the oracle's chains at those nodes read)
+    sample = sample_nodes(mesh, 600, 1234)
+    sample_t = torch.from_numpy(sample).to(dev)
+    samples = {"nodes": sample, "surface": s.cpu().numpy(), "trend": trend}
     for dname, dtype, esize in (("f64", torch.float64, 8), ("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
         f = f64.to(dtype)
         g = torch.empty((V, L, 2), dtype=dtype, device=dev)
@@ -202,29 +223,25 @@ def run_gpu(args):
         cons = float((cs.abs() / ca).max().item())
         outs = {"gradient": g, "divergence": d, "laplacian": lp, "gradient_adjoint": fT,
                 "divergence_adjoint": gT}
-        if dname == "f64":
-            refs = {k: v.clone() for k, v in outs.items()}
-        err = {}
+        # rows at the sample nodes, compared with the FP64 oracle in the CPU leg
         for k, v in outs.items():
-            r = refs[k]
-            err[k] = float(f"{(torch.linalg.vector_norm((v.double() - r).flatten()) / torch.linalg.vector_norm(r.flatten())).item():.3g}")
+            samples[f"{dname}:{k}"] = v[sample_t].double().cpu().numpy()
         sweeps = sum(OP_SWEEPS[op] for op in OPS)
         codes = {"f64": pa.F64, "f32": pa.F32, "bf16": pa.BF16}
         for op, name in kernel_names(pa, mesh, codes[dname], L).items():
             per_op[op]["kernel"] = name
         results[dname] = {"ms_per_step": round(t_step * 1e3, 4),
                           "edge_updates_s": float(f"{sweeps * E * L / t_step:.4g}"),
-                          "per_op": per_op, "curl_ops": extra, "rel_l2_vs_f64": err,
-                          "conservation_max_rel": cons}
+                          "per_op": per_op, "curl_ops": extra, "conservation_max_rel": cons}
         log(f"{dname}: {t_step * 1e3:.3f} ms/step, " +
             ", ".join(f"{op} {per_op[op]['ms']:.3f}ms {per_op[op]['hbm_frac'] * 100:.0f}%" for op in OPS))
         del f, g, d, lp, fT, gT, outs
         torch.cuda.empty_cache()
     if not args.skip_remap:
         results["remap"] = run_remap(args, pa, mesh, f64)
-    del refs, f64
+    del f64
     torch.cuda.empty_cache()
-    return mesh, results
+    return mesh, results, samples
 
 
 def run_remap(args, pa, mesh, f64):
@@ -315,17 +332,32 @@ def run_batched(args):
                         "divergence_adjoint": (d, gT)})
     torch.cuda.synchronize()
     log(f"batched: O640 mesh and 64 tracer fields (sum of levels {sum(levels)}) in {time.time() - t0:.1f}s")
-    plan = pa.Batch(mesh, tracers)
     reps = max(2, min(args.steps, 5))
-    plan.graph_launch()
-    torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
+
+    def time_graph(plan):
         plan.graph_launch()
-    b.record()
-    torch.cuda.synchronize()
-    t_graph = a.elapsed_time(b) / reps
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            plan.graph_launch()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # the tracers' field launches replayed as a graph, the persistent plan at
+    # its default shape, then the persistent plan after the autotuner
+    fields = pa.Batch(mesh, tracers, tune={"batch_mode": 2})
+    t_fields = time_graph(fields)
+    fields.close()
+    plan = pa.Batch(mesh, tracers)
+    t_default = time_graph(plan)
+    t0 = time.time()
+    shapes, tune_ms = plan.tune(reps=2)
+    tuned = {op: {k: sh[k] for k in ("batch_mode", "tile_kb", "batch_claim", "waves_per_block")}
+             for op, sh in shapes.items()}
+    log(f"batched: tuned in {time.time() - t0:.1f}s ({tune_ms:.2f} ms): {tuned}")
+    t_graph = time_graph(plan)
     a.record()
     for _ in range(reps):
         for tr in tracers:
@@ -339,49 +371,163 @@ def run_batched(args):
     sl = sum(levels)
     by = 4 * 3 * 4 * V * sl + 4 * GEOM_BYTES_PER_NODE * V * len(levels)
     out = {"workload": "O640, 64 tracers, levels from {1,19,60,91,137} (seed 1005), FP32: grad, div, "
-                       "grad adjoint, div adjoint",
+                       "grad adjoint, div adjoint, one persistent launch per operator, graph-replayed, "
+                       "autotuned",
            "sum_levels": sl, "graph_ms": round(t_graph, 3),
            "edge_updates_s": float(f"{4 * E * sl / (t_graph * 1e-3):.4g}"),
            "alg_GB_s": round(by / (t_graph * 1e-3) / 1e9, 1),
+           "hbm_frac": round(by / (t_graph * 1e-3) / HBM_PEAK, 4),
+           "tuned_shapes": tuned,
+           "default_shape_graph_ms": round(t_default, 3),
+           "field_launch_graph_ms": round(t_fields, 3),
            "single_field_ms": round(t_single, 3),
            "speedup_over_single_field": round(t_single / t_graph, 3)}
-    log(f"batched: graph {t_graph:.2f} ms, single-field calls {t_single:.2f} ms")
+    log(f"batched: persistent graph {t_graph:.2f} ms (default shape {t_default:.2f}), field-launch graph "
+        f"{t_fields:.2f} ms, single-field calls {t_single:.2f} ms")
     del tracers, plan
     torch.cuda.empty_cache()
     return out
 
 
-def run_cpu_baseline(grid, levels, nlev_sample, gpu_mesh_coords=None):
-    """Time the FP64 oracle (as it stands) on a level sample of the same
-    workload: same mesh, first `nlev_sample` levels, one full step."""
-    import numpy as np
+POOL_MAX = 16   # worker processes at most: the host's CPU share per GPU
 
-    import oracle
-    import workloads as W
+
+def host_description():
+    """CPU model, usable cores and RAM of this host."""
+    model, ram = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0)), "ram_GiB": ram}
+
+
+_LEG = {}   # oracle mesh and input of the CPU leg, shared with forked workers
+
+
+def _oracle_step(k0, k1):
+    """One full step of the FP64 oracle on levels [k0, k1) of the workload."""
     from oracle import nabla
-
-    t0 = time.time()
-    m = oracle.build_mesh(grid)
-    geo = oracle.build_dual(m)
-    log(f"oracle mesh {grid} built in {time.time() - t0:.1f}s")
-    co = (m.grid.lon, m.grid.sinlat, m.grid.coslat)
-    s, trend = W.workload_o1280(co, nlev=levels)
-    f = s[:, None] + trend[None, :nlev_sample]
-    t0 = time.perf_counter()
+    m, geo, s, trend = _LEG["mesh"], _LEG["geo"], _LEG["surface"], _LEG["trend"]
+    f = s[:, None] + trend[None, k0:k1]
     g = nabla.gradient(m, geo, f)
     d = nabla.divergence(m, geo, g)
     nabla.laplacian(m, geo, f)
     nabla.gradient_adjoint(m, geo, g)
     nabla.divergence_adjoint(m, geo, d)
     nabla.conservation(m, geo, d)
-    t = time.perf_counter() - t0
+
+
+def _pool_worker(block):
+    t0 = time.perf_counter()
+    _oracle_step(*block)
+    return time.perf_counter() - t0
+
+
+def cpu_leg(path):
+    """The oracle side of the benchmark, run in a child process that never
+    touches the GPU: (1) the FP64 oracle at the sampled nodes, from the same
+    input, against the GPU outputs of every dtype; (2) the oracle's time for
+    one full step on a bounded level sample, in one process and in a pool of
+    processes over level blocks (levels are independent)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    from oracle import nabla
+
+    z = np.load(path, allow_pickle=False)
+    grid, nlev_sample = str(z["grid"]), int(z["nlev_sample"])
+    s, trend, nodes = z["surface"], z["trend"], z["nodes"]
+    L = trend.size
+    t0 = time.time()
+    m = oracle.build_mesh(grid)
+    geo = oracle.build_dual(m)
+    log(f"oracle mesh {grid} built in {time.time() - t0:.1f}s")
+    _LEG.update(mesh=m, geo=geo, surface=s, trend=trend)
+
+    # (1) errors at the sampled nodes against the FP64 chains of the step:
+    # gradient G f, Laplacian, divergence of the gradient D G f (= the
+    # Laplacian), gradient adjoint G^T G f, divergence adjoint D^T D G f
+    def get_f(idx):
+        return s[idx][:, None] + trend[None, :]
+    ref = {}
+    _, ref["gradient"] = nabla.gradient_at(m, geo, get_f, nodes)
+    _, ref["laplacian"] = nabla.laplacian_at(m, geo, get_f, nodes)
+    ref["divergence"] = ref["laplacian"]
+    ring_nodes, ring_eids = nabla._incident(m, nodes)
+    ring = np.unique(np.concatenate([ring_nodes, m.edges[ring_eids].ravel()]))
+    lut = np.full(m.nnodes, -1)
+    lut[ring] = np.arange(ring.size)
+    _, g_ring = nabla.gradient_at(m, geo, get_f, ring)
+    _, ref["gradient_adjoint"] = nabla.gradient_adjoint_at(m, geo, lambda idx: g_ring[lut[idx]], nodes)
+    _, l_ring = nabla.laplacian_at(m, geo, get_f, ring)
+    _, ref["divergence_adjoint"] = nabla.divergence_adjoint_at(m, geo, lambda idx: l_ring[lut[idx]], nodes)
+    errors = {}
+    for key in z.files:
+        if ":" not in key:
+            continue
+        dname, op = key.split(":")
+        a, r = z[key], ref[op]
+        errors.setdefault(dname, {})[op] = {
+            "rel_l2": float(f"{np.linalg.norm(a - r) / np.linalg.norm(r):.3g}"),
+            "max_rel": float(f"{np.abs(a - r).max() / np.abs(r).max():.3g}")}
+    log("errors vs the FP64 oracle at sampled nodes: " +
+        "; ".join(f"{d} " + ", ".join(f"{o} {v['rel_l2']:.2g}" for o, v in e.items()) for d, e in errors.items()))
+
+    # (2) timing: one process on levels 0..nlev_sample-1, then one worker per
+    # core (at most POOL_MAX), each on its own block of nlev_sample levels
     E = m.nedges
-    log(f"oracle step on {nlev_sample} levels: {t:.1f}s")
-    return {"value": float(f"{6 * E * nlev_sample / t:.4g}"), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"one full step (grad, div, lap, both adjoints, conservation) of the FP64 NumPy oracle "
-                      f"on the {grid} mesh, levels 0..{nlev_sample - 1} of the {levels}-level workload; "
-                      f"single process (NumPy bincount scatter is single-threaded)",
-            "seconds": round(t, 2)}
+    t0 = time.perf_counter()
+    _oracle_step(0, nlev_sample)
+    t1 = time.perf_counter() - t0
+    log(f"oracle step on {nlev_sample} levels, one process: {t1:.1f}s")
+    nw = max(1, min(POOL_MAX, len(os.sched_getaffinity(0)), L // nlev_sample))
+    blocks = [(w * nlev_sample, (w + 1) * nlev_sample) for w in range(nw)]
+    with mp.get_context("fork").Pool(nw) as pool:
+        t0 = time.perf_counter()
+        pool.map(_pool_worker, blocks, chunksize=1)
+        tp = time.perf_counter() - t0
+    log(f"oracle step on {nw} x {nlev_sample} levels, {nw} processes: {tp:.1f}s")
+    host = host_description()
+    single = float(f"{6 * E * nlev_sample / t1:.4g}")
+    pooled = float(f"{6 * E * nw * nlev_sample / tp:.4g}")
+    base = {"value": pooled, "unit": UNIT, "cores": nw, "kind": "oracle",
+            "sample": f"one full step (grad, div, lap, both adjoints, conservation) of the FP64 NumPy oracle on "
+                      f"the {grid} mesh; {nw} processes (fork pool) over level blocks of {nlev_sample} levels "
+                      f"(levels 0..{nw * nlev_sample - 1} of the {L}-level workload), wall time; NumPy's "
+                      f"scatter is single-threaded, so one process uses one core",
+            "seconds": round(tp, 2),
+            "single_process": {"value": single, "cores": 1, "levels": nlev_sample, "seconds": round(t1, 2)},
+            "host": host}
+    return {"cpu_baseline": base, "errors_vs_oracle": errors, "sample_nodes": int(nodes.size)}
+
+
+def run_cpu_baseline(args, samples):
+    """Runs cpu_leg in a child process (a fresh interpreter that never
+    initialises the GPU, so it may fork its worker pool) on the input surface
+    and the sampled GPU outputs handed over in a temporary .npz."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "leg.npz")
+        np.savez(path, grid=np.array(args.grid), nlev_sample=np.array(args.cpu_levels), **samples)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", path],
+                           stdout=subprocess.PIPE, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"the oracle leg failed with status {r.returncode}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -397,7 +543,11 @@ def main():
     ap.add_argument("--skip-remap", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
+    ap.add_argument("--cpu-leg", metavar="NPZ", help=argparse.SUPPRESS)   # the oracle child process
     args = ap.parse_args()
+    if args.cpu_leg:
+        print(json.dumps(cpu_leg(args.cpu_leg)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X and has no "
               "multi-GPU path (levels and tracers would shard with no communication). Use --gpus 1.",
@@ -412,7 +562,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    mesh, res = run_gpu(args)
+    mesh, res, samples = run_gpu(args)
     V, E, L = mesh.nnodes, mesh.nedges, args.levels
     f32 = res["f32"]
     dom = max((op for op in OPS), key=lambda op: f32["per_op"][op]["ms"])
@@ -425,9 +575,10 @@ def main():
             "alg_bytes_per_launch": dbytes,
             "traffic": traffic}
     batched = None if args.skip_batched else run_batched(args)
-    cpu = None
+    cpu, errors, nsample = None, None, None
     if not args.skip_cpu:
-        cpu = run_cpu_baseline(args.grid, L, args.cpu_levels)
+        leg = run_cpu_baseline(args, samples)
+        cpu, errors, nsample = leg["cpu_baseline"], leg["errors_vs_oracle"], leg["sample_nodes"]
     out = {
         "metric": METRIC, "value": f32["edge_updates_s"], "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"],
@@ -441,6 +592,11 @@ def main():
         "fp64": {"ms_per_step": res["f64"]["ms_per_step"], "edge_updates_s": res["f64"]["edge_updates_s"]},
         "bf16": {"ms_per_step": res["bf16"]["ms_per_step"], "edge_updates_s": res["bf16"]["edge_updates_s"]},
         "f32_speedup_over_f64": round(res["f64"]["ms_per_step"] / f32["ms_per_step"], 3),
+        "errors_vs_fp64_oracle": None if errors is None else {
+            "sample": f"{nsample} nodes (polar rows, degree 5/7, row starts, equator, random) x {L} levels; "
+                      "FP64 oracle chains from the same FP64 input (divergence of the gradient and the "
+                      "adjoints of the step's chain); FP32 and BF16 include the rounding of the input",
+            **errors},
         "batched_o640": batched,
         "remap": res.get("remap"),
         "detail": {k: v for k, v in res.items() if k != "remap"},

@@ -350,26 +350,41 @@ typedef struct {
                                columns when 48 (1-ring) or 96 (two-ring)
                                columns fit the budget, else equal chunks);
                                ignored if one node's stencil would not fit    */
-  int32_t batch_mode;       /* batched plans: 1 one persistent launch per
-                               operator over all tracers; 2 (the default) the
+  int32_t batch_mode;       /* batched plans: 1 (the default) one persistent
+                               launch per operator over all tracers, on the
+                               LDS tiles of the one-tile form (tile_kb,
+                               band_rows, run_nodes, tile_levels and
+                               waves_per_block shape it, tile_wgs_per_cu caps
+                               its workgroups per CU; an operator whose tiles
+                               do not fit runs as field launches); 2 the
                                single-field launch of each (operator, tracer)
                                with the mesh's shapes, operators outermost    */
+  int32_t batch_claim;      /* batched persistent form: consecutive tiles a
+                               workgroup takes per claim on its XCD's work
+                               counter, 1..64 (0: 4)                          */
 } atlas_tune_t;
 
 typedef struct atlas_batch_s* atlas_batch_t;
 
 /* Create a plan: validates descriptors (host array of ntracers entries,
- * copied), uploads a device work table, and fixes the launch shape (tune may
- * be NULL).  op_mask is an OR of ATLAS_OP_* bits; every tracer must give
- * in/out pointers for every selected operator.  dtype: ATLAS_F32 or
- * ATLAS_F64.  The plan owns its device table until atlas_batch_free. */
+ * copied), fixes the launch shape (tune may be NULL) and, for the persistent
+ * form, builds each operator's LDS tiling and node records on the mesh (kept
+ * with the mesh) and uploads the plan's work tables: per tracer its fields,
+ * level chunk and work items (tiles x chunks), and per XCD of the GPU the
+ * count of items before each tracer (each XCD takes an equal contiguous share
+ * of every tracer's tiles).  op_mask is an OR of ATLAS_OP_* bits; every
+ * tracer must give in/out pointers for every selected operator.  dtype:
+ * ATLAS_F32 or ATLAS_F64.  The plan owns its work tables until
+ * atlas_batch_free. */
 int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* descs,
                        int32_t ntracers, uint32_t op_mask, const atlas_tune_t* tune,
                        atlas_batch_t* out);
 
 /* Enqueue the plan's work on `stream`, operators in the order of the bits
- * above: with batch_mode 1 one persistent launch per operator; otherwise the
- * single-field launch of every tracer for each operator.  The persistent form
+ * above: in the persistent form one launch per operator (as many workgroups
+ * as the CUs hold at once, each walking its XCD's share of the (tracer,
+ * tile, chunk) items); with batch_mode 2 the single-field launch of every
+ * tracer for each operator.  The persistent form
  * allocates nothing and never synchronises; the field form does so only the
  * first time a (operator, dtype, level count) is used on the mesh, when it
  * builds node orders, tilings and records -- after one eager run it too may be
@@ -384,11 +399,17 @@ int atlas_batch_graph_launch(atlas_batch_t plan, void* stream);
 
 void atlas_batch_free(atlas_batch_t plan);
 
-/* Time candidate launch shapes of a plan (`reps` runs each after one warm-up,
- * HIP events on `stream`, which it synchronises; the plan's fields are read
- * and overwritten).  Re-uploads the plan's work table for each candidate,
- * keeps the fastest shape in the plan, drops any captured graph, and writes
- * the shape to *best and its mean time per run in milliseconds to *best_ms. */
+/* Time candidate launch shapes of a plan, each operator's launch on its own
+ * (`reps` runs each after one warm-up, HIP events on `stream`, which it
+ * synchronises; the plan's fields are read and overwritten): the field form,
+ * then the persistent form over tile LDS budgets, tiles per claim and waves
+ * per workgroup.  Keeps each operator's fastest shape in the plan
+ * (re-uploading its work tables), drops any captured graph, and writes
+ * best[b] for each operator bit b of the plan (best has 4 entries, in the
+ * order gradient, divergence, gradient adjoint, divergence adjoint; entries
+ * of operators not in the plan are left as they were) and to *best_ms the
+ * sum over the plan's operators of their fastest times per run, in
+ * milliseconds. */
 int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_t* best,
                      float* best_ms);
 

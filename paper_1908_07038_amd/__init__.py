@@ -49,7 +49,7 @@ class TuneShape(ctypes.Structure):
                 ("lds_tiles", ctypes.c_int32), ("tile_kb", ctypes.c_int32),
                 ("tile_waves", ctypes.c_int32), ("producer_waves", ctypes.c_int32),
                 ("tile_wgs_per_cu", ctypes.c_int32), ("tile_levels", ctypes.c_int32),
-                ("batch_mode", ctypes.c_int32)]
+                ("batch_mode", ctypes.c_int32), ("batch_claim", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

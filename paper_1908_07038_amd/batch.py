@@ -1,5 +1,11 @@
-"""Batched multi-tracer plans: one persistent launch per operator over many
-fields with different level counts, optionally replayed as a HIP graph."""
+"""Batched multi-tracer plans over many fields with different level counts.
+
+By default each operator is one persistent launch over every tracer: the
+workgroups of each XCD walk that XCD's share of the (tracer, tile, level
+chunk) items on the LDS tiles of the single-field one-tile form, with the
+same arithmetic per output element, so results equal the single-field calls
+bit for bit.  ``tune={"batch_mode": 2}`` runs the tracers' single-field
+launches instead.  Either form can be replayed as a HIP graph."""
 
 import ctypes
 
@@ -71,7 +77,8 @@ class Batch:
         self._h = h
 
     def run(self):
-        """Enqueue one persistent launch per operator on the current stream."""
+        """Enqueue the plan on the current stream: one persistent launch per
+        operator (or the field launches with ``batch_mode`` 2)."""
         _check(lib().atlas_batch_run(self._h, _stream(self.device_tensor)))
 
     def graph_launch(self):
@@ -79,11 +86,15 @@ class Batch:
         _check(lib().atlas_batch_graph_launch(self._h, _stream(self.device_tensor)))
 
     def tune(self, reps=3):
-        best = TuneShape()
+        """Time the field form and persistent shapes of each operator on the
+        plan's own fields (overwriting its outputs); keeps each operator's
+        fastest shape in the plan.  Returns ({operator name: shape dict},
+        ms per run of the whole plan)."""
+        best = (TuneShape * 4)()
         ms = ctypes.c_float()
-        _check(lib().atlas_batch_tune(self._h, reps, _stream(self.device_tensor), ctypes.byref(best),
-                                      ctypes.byref(ms)))
-        return best.as_dict(), ms.value
+        _check(lib().atlas_batch_tune(self._h, reps, _stream(self.device_tensor), best, ctypes.byref(ms)))
+        shapes = {n: best[_BIT[b]].as_dict() for n, b in _OPS.items() if self.mask & b}
+        return shapes, ms.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -44,6 +44,9 @@ def _commands():
             "-fno-builtin-sincos", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include")]
     dev = [hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # work-counter claims stay plain atomics whose result is read
+           # late (no wave-level rewrite that waits for it at once)
+           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
            "-Wno-unused-command-line-argument"]
     objs = []
     cmds = []

@@ -255,6 +255,7 @@ void shape_out(const Shape& s, atlas_tune_t* t) {
   t->tile_wgs_per_cu = s.tile_wgs_per_cu;
   t->tile_levels = s.tile_levels;
   t->batch_mode = s.batch_mode;
+  t->batch_claim = s.batch_claim;
 }
 
 int check_shape(Shape& s, const atlas_tune_t* t) {
@@ -305,6 +306,8 @@ int check_shape(Shape& s, const atlas_tune_t* t) {
   s.tile_levels = t->tile_levels;
   if (t->batch_mode < 0 || t->batch_mode > 2) return fail(ATLAS_EINVAL, "batch_mode must be 0, 1 or 2");
   s.batch_mode = t->batch_mode;
+  if (t->batch_claim < 0 || t->batch_claim > 64) return fail(ATLAS_EINVAL, "batch_claim must be 0..64");
+  s.batch_claim = t->batch_claim;
 
   return ATLAS_OK;
 }
@@ -1001,15 +1004,26 @@ done:
 
 // ---- batched plans ------------------------------------------------------------
 
+// Persistent tiled launch of one operator of a plan.
+struct BatchOp {
+  bool tiled = false;       // else the tracers' single-field launches
+  BatchTile* tr = nullptr;  // device [ntracers]
+  int32_t* pre = nullptr;   // device [8][ntracers + 1]
+  int32_t* ctr = nullptr;   // device [kBatchCounterInts] work counters (zero between launches)
+  uint32_t lds = 0;
+  int waves = 0;
+  int umax = 1;             // largest slice count of the tracers
+  int32_t claim = kDefaultBatchClaim;   // tiles per work claim
+  int64_t grid = 0;
+};
+
 struct atlas_batch_s {
   atlas_mesh_t mesh = nullptr;
-  NodeOrder order;                  // owned by the mesh
   int dtype = 0;
   uint32_t mask = 0;
-  Shape shape;
+  Shape shape[4];           // launch shape of each operator
   std::vector<atlas_tracer_desc_t> descs;
-  BatchItem* items[4] = {};
-  int64_t total[4] = {};
+  BatchOp ops[4];
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1020,84 +1034,168 @@ struct atlas_batch_s {
     exec = nullptr;
     graph = nullptr;
   }
+  void release_tables() {
+    for (BatchOp& bo : ops) {
+      if (bo.tr) (void)hipFree(bo.tr);
+      if (bo.pre) (void)hipFree(bo.pre);
+      if (bo.ctr) (void)hipFree(bo.ctr);
+      bo = BatchOp();
+    }
+  }
   ~atlas_batch_s() {
     if (!mesh) return;
     DeviceGuard g(mesh->device);
     release_graph();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
-    for (auto* p : items)
-      if (p) (void)hipFree(p);
+    release_tables();
   }
 };
 
 namespace {
 
-// (Re)build the device work tables of a plan for its current shape.
-int plan_upload(atlas_batch_s* b) {
-  const int64_t V = b->mesh->host.V;
-  try {
-    b->order = b->mesh->order(b->shape);
-  } catch (const std::bad_alloc&) {
-    return fail(ATLAS_ENOMEM, "cannot allocate the node order");
-  } catch (const std::exception& ex) {
-    return fail(ATLAS_EHIP, ex.what());
+// Persistent form (batch_mode 0 or 1) unless field launches are asked for.
+bool plan_persistent(const Shape& sh) { return sh.batch_mode != 2; }
+
+// Level count whose tiling a tracer of L levels uses: L rounded up to a
+// power of two, at most the plan's largest L.  Tracers of similar depth share
+// a tiling; each tiling packs about as many columns as its single-field
+// launch would, so short columns still fill the tile's waves.
+int bucket_levels(int L, int Lmax) {
+  int p = 1;
+  while (p < L) p <<= 1;
+  return std::min(p, Lmax);
+}
+
+// Sets up the persistent tiled launch of operator o: for each level bucket
+// the tiling and node records of the single-field one-tile form, each
+// tracer's chunk (at most its tiling's) and slices, the per-XCD item counts,
+// the LDS size (largest tile plus read-past tail over the tracers) and the
+// grid (as many workgroups as the CUs hold at once).  Leaves bo.tiled false
+// when some tracer's tiles do not fit.
+int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
+  int Lmax = 1;
+  for (const atlas_tracer_desc_t& d : b->descs) Lmax = std::max(Lmax, d.nlev);
+  // tile defaults of the long-column launch, also for batches of short columns
+  const Shape sh = resolve_shape(o, b->dtype, std::max(Lmax, 33), b->shape[o]);
+  if (sh.lds_tiles != 3) return ATLAS_OK;
+  const int ntr = (int)b->descs.size();
+  std::map<int, std::pair<DevTiles, const void*>> tilings;
+  std::vector<BatchTile> tr(ntr);
+  std::vector<int32_t> pre(8 * (size_t)(ntr + 1), 0);
+  int64_t lds = 0;
+  for (int t = 0; t < ntr; ++t) {
+    BatchTile& d = tr[t];
+    d.L = b->descs[t].nlev;
+    const int Lb = bucket_levels(d.L, Lmax);
+    auto it = tilings.find(Lb);
+    if (it == tilings.end()) {
+      const TileGeom tg = tile_geom(o, b->dtype, Lb, sh);
+      if (tg.KL < 1) return ATLAS_OK;
+      try {
+        DevTiles dt = b->mesh->tiles(tg, sh);
+        dt.KL = tg.KL;
+        dt.nchunks = tg.nchunks;
+        const void* rec = b->mesh->tile_records(tg, sh, dt, o, b->dtype, nullptr);
+        it = tilings.emplace(Lb, std::make_pair(dt, rec)).first;
+      } catch (const std::bad_alloc&) {
+        return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
+      } catch (const std::exception& ex) {
+        return fail(ATLAS_EHIP, ex.what());
+      }
+    }
+    const DevTiles& dt = it->second.first;
+    d.in = b->descs[t].in[o];
+    d.out = b->descs[t].out[o];
+    d.info = dt.info;
+    d.segs = dt.segs;
+    d.rec = static_cast<const char*>(it->second.second);
+    d.KL = std::min(dt.KL, d.L);
+    d.nchunks = (d.L + d.KL - 1) / d.KL;
+    d.U = tile_slices(d.KL, sh);
+    bo.umax = std::max(bo.umax, d.U);
+    d.nitems = dt.ntiles * d.nchunks;
+    lds = std::max(lds, (int64_t)dt.lds_bytes + tile_tail_bytes(o, b->dtype, d.KL, d.L, d.U));
+    for (int x = 0; x < 8; ++x) {
+      const int64_t share = (x + 1) * d.nitems / 8 - x * d.nitems / 8;
+      const int64_t next = (int64_t)pre[x * (ntr + 1) + t] + share;
+      if (next > INT32_MAX) return fail(ATLAS_ESHAPE, "too many batched work items");
+      pre[x * (ntr + 1) + t + 1] = (int32_t)next;
+    }
   }
+  bo.waves = sh.waves_per_block;
+  bo.claim = sh.batch_claim > 0 ? sh.batch_claim : kDefaultBatchClaim;
+  const int n = lds <= (int64_t)160 * 1024 ? tiles_batched_per_cu(o, b->dtype, (uint32_t)lds, bo.waves, bo.umax) : 0;
+  if (n < 1) return ATLAS_OK;   // does not launch with this shape: field launches
+  const int per_cu = sh.tile_wgs_per_cu > 0 ? std::min(sh.tile_wgs_per_cu, n) : n;
+  bo.grid = std::max<int64_t>(8, (int64_t)per_cu * b->mesh->num_cus / 8 * 8);
+  bo.lds = (uint32_t)lds;
+  void* p = nullptr;
+  if (hipMalloc(&p, tr.size() * sizeof(BatchTile)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ATLAS_ENOMEM, "cannot allocate batch table");
+  }
+  bo.tr = static_cast<BatchTile*>(p);
+  if (hipMalloc(&p, pre.size() * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ATLAS_ENOMEM, "cannot allocate batch table");
+  }
+  bo.pre = static_cast<int32_t*>(p);
+  if (hipMalloc(&p, kBatchCounterInts * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ATLAS_ENOMEM, "cannot allocate batch counters");
+  }
+  bo.ctr = static_cast<int32_t*>(p);
+  hipError_t e = hipMemcpy(bo.tr, tr.data(), tr.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bo.pre, pre.data(), pre.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  // zero once here, outside any capture; every launch leaves them zero
+  if (e == hipSuccess) e = hipMemset(bo.ctr, 0, kBatchCounterInts * sizeof(int32_t));
+  if (e != hipSuccess) return hip_fail(e, "batch table upload");
+  bo.tiled = true;
+  return ATLAS_OK;
+}
+
+// (Re)build the device work tables of a plan for its operators' shapes.
+int plan_upload(atlas_batch_s* b) {
+  b->release_tables();
   for (int o = 0; o < 4; ++o) {
-    if (b->items[o]) {
-      (void)hipFree(b->items[o]);
-      b->items[o] = nullptr;
-    }
-    if (!(b->mask & (1u << o))) continue;
-    std::vector<BatchItem> host(b->descs.size());
-    int64_t tile = 0;
-    for (size_t t = 0; t < b->descs.size(); ++t) {
-      const int L = b->descs[t].nlev;
-      host[t].in = b->descs[t].in[o];
-      host[t].out = b->descs[t].out[o];
-      host[t].nlev = L;
-      host[t].window = uses_window(o, L, b->shape) ? 1 : 0;
-      host[t].lanes = host[t].window ? 64 : lanes_per_node(L, b->shape);
-      host[t].unroll = host[t].window ? window_slices(L, b->shape) : slices_per_iter(L, b->shape);
-      host[t].tile_begin = tile;
-      tile += tiles_for(o, b->order, V, L, b->shape);
-    }
-    b->total[o] = tile;
-    void* p = nullptr;
-    if (hipMalloc(&p, host.size() * sizeof(BatchItem)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ATLAS_ENOMEM, "cannot allocate batch table");
-    }
-    b->items[o] = static_cast<BatchItem*>(p);
-    hipError_t e = hipMemcpy(p, host.data(), host.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "batch table upload");
+    if (!(b->mask & (1u << o)) || !plan_persistent(b->shape[o])) continue;
+    int rc = plan_op(b, o, b->ops[o]);
+    if (rc) return rc;
   }
   return ATLAS_OK;
 }
 
-// Persistent form: one launch per operator over every tracer.  Field form
-// (the default): the single-field launch of each (operator, tracer), with the
-// mesh's shapes, operators outermost -- the same order of work.
-bool plan_persistent(const Shape& sh) { return sh.batch_mode == 1; }
-
-int plan_run(atlas_batch_s* b, hipStream_t st, const Shape& sh) {
-  const int64_t V = b->mesh->host.V;
-  if (!plan_persistent(sh)) {
-    for (int o = 0; o < 4; ++o) {
-      if (!(b->mask & (1u << o))) continue;
-      for (const atlas_tracer_desc_t& d : b->descs) {
-        int rc = run_op(b->mesh, o, b->dtype, d.nlev, d.in[o], d.out[o], st);
-        if (rc) return rc;
-      }
-    }
-    return ATLAS_OK;
+// One operator over every tracer: one persistent launch, or the tracers'
+// single-field launches in order.
+int plan_run_op(atlas_batch_s* b, int o, hipStream_t st) {
+  const BatchOp& bo = b->ops[o];
+  if (bo.tiled) {
+    hipError_t e = launch_tiles_batched(o, b->dtype, bo.tr, bo.pre, (int)b->descs.size(), bo.ctr, bo.claim, bo.lds,
+                                        bo.waves, bo.grid, bo.umax, st);
+    return e != hipSuccess ? hip_fail(e, kOpName[o]) : ATLAS_OK;
   }
-  for (int o = 0; o < 4; ++o) {
-    if (!(b->mask & (1u << o))) continue;
-    hipError_t e = launch_batched(o, b->dtype, b->mesh->tables(b->dtype), b->order, V, b->items[o],
-                                  (int)b->descs.size(), b->total[o], sh, b->mesh->num_cus, st);
-    if (e != hipSuccess) return hip_fail(e, kOpName[o]);
+  for (const atlas_tracer_desc_t& d : b->descs) {
+    int rc = run_op(b->mesh, o, b->dtype, d.nlev, d.in[o], d.out[o], st);
+    if (rc) return rc;
   }
   return ATLAS_OK;
+}
+
+// Operators outermost, in the order of their bits.
+int plan_run(atlas_batch_s* b, hipStream_t st) {
+  for (int o = 0; o < 4; ++o) {
+    if (!(b->mask & (1u << o))) continue;
+    int rc = plan_run_op(b, o, st);
+    if (rc) return rc;
+  }
+  return ATLAS_OK;
+}
+
+// Whether every operator of the plan runs as one persistent launch.
+bool plan_all_tiled(const atlas_batch_s* b) {
+  for (int o = 0; o < 4; ++o)
+    if ((b->mask & (1u << o)) && !b->ops[o].tiled) return false;
+  return true;
 }
 
 }  // namespace
@@ -1139,10 +1237,11 @@ int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* 
   b->mesh = mesh;
   b->dtype = dtype;
   b->mask = op_mask;
-  if ((rc = check_shape(b->shape, tune))) {
+  if ((rc = check_shape(b->shape[0], tune))) {
     delete b;
     return rc;
   }
+  for (int o = 1; o < 4; ++o) b->shape[o] = b->shape[0];
   b->descs.assign(descs, descs + ntracers);
   DeviceGuard g(mesh->device);
   if ((rc = plan_upload(b))) {
@@ -1156,7 +1255,7 @@ int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* 
 int atlas_batch_run(atlas_batch_t plan, void* stream) {
   if (!plan) return fail(ATLAS_EINVAL, "plan is NULL");
   DeviceGuard g(plan->mesh->device);
-  return plan_run(plan, (hipStream_t)stream, plan->shape);
+  return plan_run(plan, (hipStream_t)stream);
 }
 
 int atlas_batch_graph_launch(atlas_batch_t plan, void* stream) {
@@ -1168,18 +1267,18 @@ int atlas_batch_graph_launch(atlas_batch_t plan, void* stream) {
       e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
     }
-    if (!plan_persistent(plan->shape)) {
+    if (!plan_all_tiled(plan)) {
       // one eager pass, in order on the caller's stream, builds every node
-      // order, tiling and record table the launches need (host work and
-      // allocation cannot be captured)
-      int rc0 = plan_run(plan, (hipStream_t)stream, plan->shape);
+      // order, tiling and record table the field launches need (host work
+      // and allocation cannot be captured)
+      int rc0 = plan_run(plan, (hipStream_t)stream);
       if (rc0) return rc0;
       e = hipStreamSynchronize((hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     }
     e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int rc = plan_run(plan, plan->capture_stream, plan->shape);
+    int rc = plan_run(plan, plan->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(plan->capture_stream, &graph);
     if (rc) {
@@ -1214,54 +1313,69 @@ int atlas_batch_tune(atlas_batch_t plan, int32_t reps, void* stream, atlas_tune_
     (void)hipEventDestroy(e0);
     return fail(ATLAS_EHIP, "hipEventCreate");
   }
-  const Shape orig = plan->shape;
-  Shape bs = orig;
-  float bestt = 1e30f;
+  Shape orig[4], bs[4];
+  float bestt[4];
+  for (int o = 0; o < 4; ++o) {
+    orig[o] = bs[o] = plan->shape[o];
+    bestt[o] = 1e30f;
+  }
   int rc = ATLAS_OK;
-  const int wpbs[] = {2, 4};
-  const int npws[] = {1, 2, 4};
-  const int bpcs[] = {2, 4, 8};
   // the field form first (its launches use the mesh's shapes), then the
-  // persistent form over workgroup shapes
-  for (int k = -1; k < 2 * 3 * 3 * 2; ++k) {
+  // persistent tiled form over the tile's LDS budget (0: each operator's
+  // default), tiles per work claim and waves per workgroup; each operator's
+  // launch is timed on its own and keeps its fastest shape
+  const int kbs[] = {0, 64, 80};
+  const int claims[] = {4, 8};
+  const int wpbs[] = {8, 16};
+  for (int k = -1; k < 3 * 2 * 2; ++k) {
     Shape s;
     if (k < 0) {
       s.batch_mode = 2;
     } else {
       s.batch_mode = 1;
-      s.waves_per_block = wpbs[k / 18];
-      s.nodes_per_wave = npws[(k / 6) % 3];
-      s.blocks_per_cu = bpcs[(k / 2) % 3];
-      s.xcd_remap = k % 2;
+      s.tile_kb = kbs[k / 4];
+      s.batch_claim = claims[(k / 2) % 2];
+      s.waves_per_block = wpbs[k % 2];
     }
-    plan->shape = s;
+    for (int o = 0; o < 4; ++o) plan->shape[o] = s;
     if (hipStreamSynchronize(st) != hipSuccess) {
       rc = fail(ATLAS_EHIP, "hipStreamSynchronize");
       goto done;
     }
     if ((rc = plan_upload(plan))) goto done;
-    if ((rc = plan_run(plan, st, s))) goto done;
-    (void)hipEventRecord(e0, st);
-    for (int r = 0; r < reps; ++r)
-      if ((rc = plan_run(plan, st, s))) goto done;
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = fail(ATLAS_EHIP, "hipEventSynchronize");
-      goto done;
-    }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    ms /= (float)reps;
-    if (ms < bestt) {
-      bestt = ms;
-      bs = s;
+    for (int o = 0; o < 4; ++o) {
+      if (!(plan->mask & (1u << o))) continue;
+      if ((rc = plan_run_op(plan, o, st))) goto done;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r)
+        if ((rc = plan_run_op(plan, o, st))) goto done;
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(ATLAS_EHIP, "hipEventSynchronize");
+        goto done;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= (float)reps;
+      if (ms < bestt[o]) {
+        bestt[o] = ms;
+        bs[o] = s;
+      }
     }
   }
-  shape_out(bs, best);
-  if (best_ms) *best_ms = bestt;
+  {
+    float total = 0.f;
+    for (int o = 0; o < 4; ++o) {
+      if (!(plan->mask & (1u << o))) continue;
+      shape_out(bs[o], best + o);
+      total += bestt[o];
+    }
+    if (best_ms) *best_ms = total;
+  }
 done:
-  // leave the plan with the best shape found (or its original one on error)
-  plan->shape = rc ? orig : bs;
+  // leave the plan with each operator's best shape (or the original ones on
+  // error)
+  for (int o = 0; o < 4; ++o) plan->shape[o] = rc ? orig[o] : bs[o];
   (void)hipStreamSynchronize(st);
   int rc2 = plan_upload(plan);
   (void)hipEventDestroy(e0);

@@ -589,44 +589,6 @@ __global__ __launch_bounds__(256) void k_win(Args a, int64_t nblocks, int remap)
   process_runs<S, OP, U>(a, lb);
 }
 
-// Persistent batched form: the global tile index space is the concatenation
-// of each tracer's blocks; every workgroup walks a contiguous range of it.
-template <class S, int OP>
-__global__ __launch_bounds__(256) void k_batched(Args base, const BatchItem* __restrict__ items, int nitems,
-                                                  int64_t total, int remap) {
-  const int64_t nb = gridDim.x;
-  const int64_t lb = logical_block(blockIdx.x, nb, remap);   // grid is a multiple of 8 when remapping
-  const int64_t per = (total + nb - 1) / nb;
-  const int64_t t0 = lb * per;
-  const int64_t t1 = t0 + per < total ? t0 + per : total;
-  int item = 0;
-  for (int64_t tile = t0; tile < t1; ++tile) {
-    // tiles ascend, so the item index only moves forward
-    while (item + 1 < nitems && items[item + 1].tile_begin <= tile) ++item;
-    Args a = base;
-    a.in = items[item].in;
-    a.out = items[item].out;
-    a.L = items[item].nlev;
-    a.P = items[item].lanes;
-    const int64_t lb2 = tile - items[item].tile_begin;
-    if constexpr (OP != OP_LAP) {
-      if (items[item].window) {
-        switch (items[item].unroll) {
-          case 1: process_runs<S, OP, 1>(a, lb2); break;
-          case 2: process_runs<S, OP, 2>(a, lb2); break;
-          default: process_runs<S, OP, 3>(a, lb2); break;
-        }
-        continue;
-      }
-    }
-    switch (items[item].unroll) {
-      case 1: process_block<S, OP, 1>(a, lb2); break;
-      case 2: process_block<S, OP, 2>(a, lb2); break;
-      default: process_block<S, OP, 3>(a, lb2); break;
-    }
-  }
-}
-
 // ---- LDS tiles -------------------------------------------------------------------
 //
 // A workgroup takes one tile: a set of nodes (a few latitude rows by one
@@ -1277,17 +1239,31 @@ template <class S, int OP, int U>
 constexpr int kTileThreads =
     (sizeof(S) == 8 && (((OP == OP_GRADLAP || OP == OP_DIVCURL) && U > 1) || (OP == OP_LAP && U == 3))) ? 512 : 1024;
 
-template <class S, int OP, int U>
-__global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, int64_t nblocks, int remap) {
-  extern __shared__ __align__(16) char lds[];
+// A device pointer read from a table, marked as global memory: accesses
+// through it compile to global (not flat) instructions, which leave the LDS
+// counter alone, so waits for LDS reads never wait for output stores.
+template <class T>
+__device__ __forceinline__ T* global_ptr(const void* slot) {
+  using G = __attribute__((address_space(1))) T*;
+  return (T*)(G)ld_const(reinterpret_cast<const uint64_t*>(slot));
+}
+
+// Workgroup barrier that orders LDS accesses only: each wave's LDS reads and
+// writes are complete before it, and visible after it, but the wave's global
+// stores stay in flight (a full __syncthreads() would wait for them too).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One (tile, level chunk) of a field by the W waves of a workgroup: copy into
+// LDS, wait, run after_copy() (all waves are past the barrier), evaluate.
+// The caller synchronises before the buffer is reused.
+template <class S, int OP, int U, class F>
+__device__ __forceinline__ void tile_work(const TileArgs& a, int64_t tile, int chunk, char* lds, int W, int wave,
+                                          int lane, F&& after_copy) {
   using R = TileRec<S, OP>;
-  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
-  if (lb >= nblocks) return;
-  const int64_t tile = lb / a.nchunks;
-  const int chunk = (int)(lb - tile * a.nchunks);
-  const int W = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
   const int k0 = chunk * a.KL;
   const int klc = a.L - k0 < a.KL ? a.L - k0 : a.KL;
   tile_copy<S, OP>(a, tile, k0, klc, lds, wave, W, lane);
@@ -1296,6 +1272,7 @@ __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, i
   const uint32_t data_off = (uint32_t)nnodes * R::kBytes;   // BF16: the offset table starts here
   __builtin_amdgcn_s_waitcnt(0);   // all counters: the direct loads have landed
   __syncthreads();
+  after_copy();
   // compute: node tn of the tile goes to wave tn mod W for whole 64-level
   // slices; a short remainder (1..32 levels) of all nodes is packed G = 64 /
   // rem nodes to a wave
@@ -1305,6 +1282,134 @@ __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, i
   if (kmain > 0)
     for (int32_t tn = wave; tn < nnodes; tn += W) tile_eval<S, OP, U>(a, lds, tn, data_off, colB, k0, kmain, lane);
   if (pack) tile_tail<S, OP>(a, lds, nnodes, data_off, colB, k0, kmain, rem, wave, W, lane);
+}
+
+template <class S, int OP, int U>
+__global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, int64_t nblocks, int remap) {
+  extern __shared__ __align__(16) char lds[];
+  const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
+  if (lb >= nblocks) return;
+  const int64_t tile = lb / a.nchunks;
+  const int chunk = (int)(lb - tile * a.nchunks);
+  const int W = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  tile_work<S, OP, U>(a, tile, chunk, lds, W, wave, lane, [] {});
+}
+
+// Persistent form over many fields (tracers) of one operator, each on its
+// own tiling (tracers of similar level counts share one).  The work items of
+// tracer t are its ntiles_t x nchunks_t (tile, chunk) pairs in tile order;
+// XCD x takes the contiguous share [x n_t / 8, (x + 1) n_t / 8) of every
+// tracer, so tiles stacked in latitude still meet in one L2, and every XCD
+// gets the same mix of long and short columns.  pre[x][t] counts the items of
+// share x before tracer t (pre[x][ntr] its total).  The workgroups b with
+// b mod 8 = x (the ones the hardware places on XCD x) take the items of share
+// x in order from a counter, `claim` consecutive items per claim (tiles
+// stacked in latitude, whose shared halo rows the workgroup then finds in
+// L2), as they become free, so the tiles in flight on an XCD stay a narrow
+// window of the order (a fixed stride lets workgroups drift apart and the
+// halo rows they share drop out of L2).  Claims are device-scope atomics,
+// which the XCDs' counters serialise; claiming several items at once and
+// giving each share's counters a cache line of their own keeps them off the
+// critical path, and each workgroup claims once ahead, so a claim's latency
+// hides behind a tile's copy.  The last workgroup of share x to finish sets
+// both of its counters back to zero for the next launch, so a graph replays
+// without a memset.  Each tracer's chunk is its own (at most its tiling's), with the
+// slice count of the single-field launch (at most UMAX).  Every wave of a
+// workgroup runs the same loop, so the barriers are reached by all.
+template <class S, int OP, int UMAX>
+__global__ __launch_bounds__(1024) void k_tile_batched(TileArgs base, const BatchTile* __restrict__ tr,
+                                                       const int32_t* __restrict__ pre, int ntr,
+                                                       int32_t* __restrict__ ctr, int32_t claim) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int32_t next_item;
+  const int W = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int x = (int)(blockIdx.x & 7u);
+  const int32_t gx = (int32_t)(gridDim.x >> 3);   // the grid is a multiple of 8
+  const int32_t* px = pre + (size_t)x * (ntr + 1);
+  const int32_t mx = ld_uniform(px + ntr);
+  int32_t* cx = ctr + kBatchCtrStride * x;         // claim counter; cx[kBatchCtrStride / 2]: finished
+  // Thread 0 holds the end of the current claim and the next claim (`ahead`):
+  // a claim made during one claim's items is used only after a later copy has
+  // been waited for, which has also waited for the claim, so no evaluation
+  // stalls on it.
+  int32_t cur_end = 0, ahead = 0;
+  if (threadIdx.x == 0) {
+    const int32_t c0 = __hip_atomic_fetch_add(cx, claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ahead = __hip_atomic_fetch_add(cx, claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    next_item = c0;
+    cur_end = c0 + claim;
+  }
+  __syncthreads();
+  // k is the same in every lane: read it into a scalar register, so the
+  // loop and the table loads below stay scalar
+  int32_t k = __builtin_amdgcn_readfirstlane(next_item);
+  // the current tracer's fields stay in registers: they are loaded again
+  // only when the item index moves past the tracer's items (k only grows)
+  int t = -1;
+  int32_t t_lo = 0, t_hi = 0;   // the tracer's items on this share: [t_lo, t_hi)
+  int64_t first = 0;            // its first item index on this share
+  int U = 1;
+  TileArgs a = base;
+  while (k < mx) {
+    if (k >= t_hi) {
+      do {
+        ++t;
+        t_hi = ld_uniform(px + t + 1);   // px[ntr] = mx > k ends the scan
+      } while (t_hi <= k);
+      t_lo = ld_uniform(px + t);
+      const BatchTile* d = tr + t;
+      a.in = global_ptr<const S>(&d->in);
+      a.out = global_ptr<S>(&d->out);
+      a.info = reinterpret_cast<const int32_t*>(ld_const(reinterpret_cast<const uint64_t*>(&d->info)));
+      a.segs = reinterpret_cast<const int32_t*>(ld_const(reinterpret_cast<const uint64_t*>(&d->segs)));
+      a.rec = reinterpret_cast<const char*>(ld_const(reinterpret_cast<const uint64_t*>(&d->rec)));
+      a.L = ld_const(&d->L);
+      a.KL = ld_const(&d->KL);
+      a.nchunks = ld_const(&d->nchunks);
+      U = ld_const(&d->U);
+      first = (int64_t)x * ld_const(&d->nitems) / 8;
+    }
+    const int64_t item = first + (k - t_lo);
+    const int64_t tile = a.nchunks == 1 ? item : item / a.nchunks;
+    const int chunk = (int)(item - tile * a.nchunks);
+    // after the copy's wait and barrier (every wave has read next_item):
+    // publish the next item, the claim's next or the first of the claim
+    // ahead (then claiming another)
+    auto advance = [&] {
+      if (threadIdx.x == 0) {
+        if (k + 1 < cur_end) {
+          next_item = k + 1;
+        } else {
+          next_item = ahead;
+          cur_end = ahead + claim;
+          ahead = __hip_atomic_fetch_add(cx, claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    };
+    // UMAX: the largest slice count of the plan's tracers; only the paths
+    // up to it are compiled in, which keeps the kernel's code small
+    if (UMAX == 1 || U == 1) tile_work<S, OP, 1>(a, tile, chunk, lds, W, wave, lane, advance);
+    else if (UMAX == 2 || U == 2) tile_work<S, OP, (UMAX < 2 ? UMAX : 2)>(a, tile, chunk, lds, W, wave, lane, advance);
+    else tile_work<S, OP, UMAX>(a, tile, chunk, lds, W, wave, lane, advance);
+    // every wave is done reading the buffer, and next_item is written; the
+    // tile's output stores need not have landed
+    lds_barrier();
+    k = __builtin_amdgcn_readfirstlane(next_item);
+  }
+  if (threadIdx.x == 0) {
+    // every claim of this workgroup (the one ahead included) is complete
+    // before its count (release); the last workgroup of the share (acquire)
+    // sets both counters back to zero
+    int32_t* fin = cx + kBatchCtrStride / 2;
+    if (__hip_atomic_fetch_add(fin, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gx - 1) {
+      __hip_atomic_store(cx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(fin, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // Packs the node records of a tiling in tile order: record q is node
@@ -1871,26 +1976,6 @@ hipError_t launch_op_t(int op, const Args& a, int U, int64_t nblocks, bool windo
   }
 }
 
-template <class S>
-hipError_t launch_batched_t(int op, const Args& a, const BatchItem* items, int nitems, int64_t total,
-                            const Shape& sh_in, int num_cus, hipStream_t st) {
-  Shape sh = sh_in;
-  if (sh.waves_per_block > 4) sh.waves_per_block = 4;
-  int64_t grid = (int64_t)sh.blocks_per_cu * num_cus;
-  if (grid > total) grid = total;
-  if (grid < 1) grid = 1;
-  const int remap = (sh.xcd_remap && grid % 8 == 0) ? 1 : 0;
-  const dim3 g((unsigned)grid), b((unsigned)(64 * sh.waves_per_block));
-  switch (op) {
-    case OP_GRAD: hipLaunchKernelGGL((k_batched<S, OP_GRAD>), g, b, 0, st, a, items, nitems, total, remap); break;
-    case OP_DIV: hipLaunchKernelGGL((k_batched<S, OP_DIV>), g, b, 0, st, a, items, nitems, total, remap); break;
-    case OP_GRADT: hipLaunchKernelGGL((k_batched<S, OP_GRADT>), g, b, 0, st, a, items, nitems, total, remap); break;
-    case OP_DIVT: hipLaunchKernelGGL((k_batched<S, OP_DIVT>), g, b, 0, st, a, items, nitems, total, remap); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 template <class S, int OP>
 hipError_t launch_tile_u(const TileArgs& a, int U, dim3 g, dim3 b, uint32_t lds, int64_t nblocks, int remap,
                          hipStream_t st) {
@@ -2346,20 +2431,101 @@ hipError_t scratch_address(int device, double** ptr) {
   return hipSuccess;
 }
 
-int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape) {
-  Shape sh = shape;
-  if (sh.waves_per_block > 4) sh.waves_per_block = 4;   // as launch_batched_t
-  return blocks_for(op, ord, V, nlev, sh);
+namespace {
+
+template <class S, int OP, int UMAX>
+hipError_t launch_tb(const TileArgs& a, const BatchTile* tr, const int32_t* pre, int ntr, int32_t* ctr, int32_t claim,
+                     uint32_t lds, int waves, int64_t grid, hipStream_t st) {
+  const void* fn = reinterpret_cast<const void*>(&k_tile_batched<S, OP, UMAX>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 g((unsigned)grid), b((unsigned)(64 * waves));
+  hipLaunchKernelGGL((k_tile_batched<S, OP, UMAX>), g, b, lds, st, a, tr, pre, ntr, ctr, claim);
+  return hipGetLastError();
 }
 
-hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V,
-                          const BatchItem* items, int nitems, int64_t total_tiles, const Shape& shape, int num_cus,
-                          hipStream_t stream) {
-  Args a = make_args(op, t, ord, V, 1, nullptr, nullptr, shape);
+template <class S, int OP>
+const void* tb_fn_u(int umax) {
+  return umax == 1   ? reinterpret_cast<const void*>(&k_tile_batched<S, OP, 1>)
+         : umax == 2 ? reinterpret_cast<const void*>(&k_tile_batched<S, OP, 2>)
+                     : reinterpret_cast<const void*>(&k_tile_batched<S, OP, 3>);
+}
+
+template <class S>
+const void* tb_fn(int op, int umax) {
+  switch (op) {
+    case OP_GRAD: return tb_fn_u<S, OP_GRAD>(umax);
+    case OP_DIV: return tb_fn_u<S, OP_DIV>(umax);
+    case OP_GRADT: return tb_fn_u<S, OP_GRADT>(umax);
+    case OP_DIVT: return tb_fn_u<S, OP_DIVT>(umax);
+    default: return nullptr;
+  }
+}
+
+template <class S, int OP>
+hipError_t launch_tb_u(const TileArgs& a, const BatchTile* tr, const int32_t* pre, int ntr, int32_t* ctr,
+                       int32_t claim, uint32_t lds, int waves, int64_t grid, int umax, hipStream_t st) {
+  switch (umax) {
+    case 1: return launch_tb<S, OP, 1>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, st);
+    case 2: return launch_tb<S, OP, 2>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, st);
+    default: return launch_tb<S, OP, 3>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, st);
+  }
+}
+
+template <class S>
+hipError_t launch_tb_t(int op, const TileArgs& a, const BatchTile* tr, const int32_t* pre, int ntr, int32_t* ctr,
+                       int32_t claim, uint32_t lds, int waves, int64_t grid, int umax, hipStream_t st) {
+  switch (op) {
+    case OP_GRAD: return launch_tb_u<S, OP_GRAD>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+    case OP_DIV: return launch_tb_u<S, OP_DIV>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+    case OP_GRADT: return launch_tb_u<S, OP_GRADT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+    case OP_DIVT: return launch_tb_u<S, OP_DIVT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int tiles_batched_per_cu(int op, int dtype, uint32_t lds, int waves, int umax) {
+  const int kop = kernel_op(op);
+  const void* fn = dtype == DT_F64 ? tb_fn<double>(kop, umax) : dtype == DT_F32 ? tb_fn<float>(kop, umax) : nullptr;
+  if (!fn || waves < 1 || waves > 16 || lds > kLdsPerCu || umax < 1 || umax > 3) return 0;
+  if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64 * waves, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+hipError_t launch_tiles_batched(int op, int dtype, const BatchTile* tr, const int32_t* pre, int ntr, int32_t* ctr,
+                                int32_t claim, uint32_t lds, int waves, int64_t grid, int umax,
+                                hipStream_t stream) {
+  const int kop = kernel_op(op);
+  if (kop != OP_GRAD && kop != OP_DIV && kop != OP_GRADT && kop != OP_DIVT) return hipErrorInvalidValue;
+  // the grid is a multiple of 8 workgroups (one share per XCD)
+  if (ntr < 1 || !ctr || claim < 1 || claim > 64 || grid < 8 || grid % 8 != 0 || grid > INT32_MAX || waves < 1 ||
+      waves > 16 || lds > kLdsPerCu || umax < 1 || umax > 3)
+    return hipErrorInvalidValue;
+  TileArgs a;   // fields, tiling and level chunking per tracer in the kernel
+  a.info = nullptr;
+  a.segs = nullptr;
+  a.rec = nullptr;
+  a.in = nullptr;
+  a.out = nullptr;
+  a.out2 = nullptr;
+  a.ntiles = 0;
+  a.L = a.KL = a.nchunks = 1;
+  a.nt = 0;
   switch (dtype) {
-    case DT_F64: return launch_batched_t<double>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
-    case DT_F32: return launch_batched_t<float>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
-    case DT_BF16: return launch_batched_t<bf16_t>(op, a, items, nitems, total_tiles, shape, num_cus, stream);
+    case DT_F64: return launch_tb_t<double>(kop, a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, stream);
+    case DT_F32: return launch_tb_t<float>(kop, a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -50,7 +50,8 @@ struct Shape {
   int producer_waves = 0;    // 0: 2; producer (copy) waves per persistent tile workgroup
   int tile_wgs_per_cu = 0;   // 0: 1; persistent tile workgroups per CU
   int tile_levels = 0;       // 0: automatic; else levels per column chunk of a tile
-  int batch_mode = 0;        // batched plans: 0 default (field launches), 1 persistent, 2 field launches
+  int batch_mode = 0;        // batched plans: 0 default (persistent), 1 persistent tiled, 2 field launches
+  int batch_claim = 0;       // batched persistent form: tiles per work claim (0: kDefaultBatchClaim)
 };
 
 constexpr int kDefaultBandRows = 32;
@@ -58,6 +59,7 @@ constexpr int kDefaultRunNodes = 16;
 constexpr int kDefaultWindowRunNodes = 64;
 constexpr int kDefaultTileKB = 48;
 constexpr int kDefaultTileRows = 4;    // LDS tiles: rows per tile (band_rows)
+constexpr int kDefaultBatchClaim = 4;  // batched persistent form: tiles per work claim
 constexpr int kDefaultTileSweep = 8;   // LDS tiles: bands swept together (run_nodes)
 inline int band_rows_of(const Shape& s) { return s.band_rows > 0 ? s.band_rows : kDefaultBandRows; }
 inline int run_nodes_of(const Shape& s) { return s.run_nodes > 0 ? s.run_nodes : kDefaultRunNodes; }
@@ -157,19 +159,39 @@ hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t 
 hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
                                 const void* in, void* out, hipStream_t stream);
 
-// Batched persistent launch over a device table of work items.
-struct BatchItem {
+// Batched persistent launch: one kernel over many fields (tracers) of one
+// operator on LDS tilings.  Per tracer: its fields, its tiling and records,
+// its level chunk (at most the tiling's), chunks per column, slices per step
+// and work items (tiles x chunks).
+struct BatchTile {
   const void* in;
   void* out;
-  int32_t nlev;
-  int32_t lanes;         // lanes_per_node(nlev)
-  int32_t unroll;        // slices per iteration (window_slices or slices_per_iter)
-  int32_t window;        // uses_window(op, nlev)
-  int64_t tile_begin;    // first global tile of this tracer
+  const int32_t* info;   // the tracer's tiling (DevTiles::info, segs) and its node records
+  const int32_t* segs;
+  const char* rec;
+  int64_t nitems;
+  int32_t L, KL, nchunks, U;
 };
-int64_t tiles_for(int op, const NodeOrder& ord, int64_t V, int nlev, const Shape& shape);
-hipError_t launch_batched(int op, int dtype, const DevTables& t, const NodeOrder& ord, int64_t V,
-                          const BatchItem* items, int nitems, int64_t total_tiles,
-                          const Shape& shape, int num_cus, hipStream_t stream);
+// tr: device [ntr] descriptors; pre: device [8][ntr + 1] item counts of each
+// XCD before each tracer (see k_tile_batched); ctr: device int32 work
+// counters (kBatchCounterInts of them), zero before the first launch (each
+// launch leaves them zero; two launches with the same counters must not
+// overlap in time); claim: consecutive items per counter claim (1..64);
+// lds: bytes per
+// workgroup (the largest tile of the tracers' tilings plus the read-past
+// tail of every tracer); grid: a multiple of 8 workgroups of `waves` waves;
+// umax: the largest U of the descriptors (1..3), which picks the kernel
+// instance.
+hipError_t launch_tiles_batched(int op, int dtype, const BatchTile* tr, const int32_t* pre, int ntr, int32_t* ctr,
+                                int32_t claim, uint32_t lds, int waves, int64_t grid, int umax,
+                                hipStream_t stream);
+// Work counters of the batched kernel: a claim counter and a finished count
+// (kBatchCtrStride / 2 further on) per XCD share, each share on its own
+// 256-byte span.
+constexpr int kBatchCtrStride = 64;
+constexpr int kBatchCounterInts = 8 * kBatchCtrStride;
+// Workgroups of the batched kernel instance one CU holds at once (registers,
+// waves and `lds` bytes of LDS), 0 if it does not launch.
+int tiles_batched_per_cu(int op, int dtype, uint32_t lds, int waves, int umax);
 
 }  // namespace atlasnabla

@@ -1,6 +1,6 @@
 """Batched multi-tracer plans over tracers with uneven level counts, in both
-forms (the default graph of the tracers' field launches, and one persistent
-launch per operator over the concatenated tile index space), eager and
+forms (the default one persistent launch per operator over every tracer's
+(tile, level chunk) items, and the tracers' field launches), eager and
 replayed as a HIP graph, must give the same bits as the single-field calls."""
 import pytest
 import torch
@@ -41,7 +41,10 @@ def _check_against_single(mesh, tracers):
             assert torch.equal(y, ref), (name, x.shape)
 
 
-MODES = {"fields": None, "persistent": {"batch_mode": 1}}
+MODES = {"persistent": None, "fields": {"batch_mode": 2},
+         "persistent_shaped": {"batch_mode": 1, "waves_per_block": 16, "band_rows": 6, "tile_levels": 64,
+                               "tile_wgs_per_cu": 2, "batch_claim": 1},
+         "persistent_claim8": {"batch_claim": 8, "tile_kb": 80, "slices_per_iter": 1}}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -78,14 +81,18 @@ def test_batch_tune_keeps_results():
     M = pa.Mesh("O16", device=0)
     tracers = _tracers(M, [137, 19, 1], torch.float32, 3)
     plan = pa.Batch(M, tracers)
-    shape, ms = plan.tune(reps=1)
+    shapes, ms = plan.tune(reps=1)
     assert ms > 0
-    for tr in tracers:
-        for _, (x, y) in tr.items():
-            y.fill_(float("nan"))
-    plan.run()
-    torch.cuda.synchronize()
-    _check_against_single(M, tracers)
+    assert set(shapes) == set(COMPS)
+    assert all(sh["batch_mode"] in (1, 2) for sh in shapes.values())
+    for launch in (plan.run, plan.graph_launch, plan.graph_launch):
+        for tr in tracers:
+            for _, (x, y) in tr.items():
+                y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        _check_against_single(M, tracers)
 
 
 @pytest.mark.parametrize("mode", list(MODES))

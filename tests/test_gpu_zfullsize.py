@@ -13,8 +13,9 @@ hold at any size.
   of sum(w' * div uv), dot-product tests, central differences on 100 seeded
   node-level entries, sampled oracle values of the adjoints.
 * O640 batched: 64 tracers with level counts drawn from {1, 19, 60, 91, 137},
-  run as the batched plan (default form) replayed as a HIP graph, bitwise
-  equal to the single-field calls and sampled against the oracle.
+  run as the batched plan (default form: one persistent launch per operator
+  over every tracer's tiles) replayed as a HIP graph, bitwise equal to the
+  single-field calls and sampled against the oracle.
 Bars as in test_gpu_parity (FP64 1e-12, FP32 1e-5 total, BF16 4e-3 kernel),
 normwise and element-wise, the element-wise bar also per level and on the
 special node groups (tests/_parity.py).
