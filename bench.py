@@ -530,6 +530,92 @@ def run_cpu_baseline(args, samples):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+# Kernel instances of one bench dtype: (op name in hbm_traffic.txt, kernel
+# operator number in the k_tile<type, op, U> template, or a kernel name prefix).
+PROFILE_STATS_CMD = ("cd /tmp && export TMPDIR=/tmp && cd <repo> && rocprofv3 --kernel-trace --stats -d <out>/stats "
+                     "-o bench -- python3 bench.py --steps 5 --warmup 2 --skip-cpu")
+PROFILE_PMC_CMD = ("cd /tmp && export TMPDIR=/tmp && cd <repo> && rocprofv3 --pmc COUNTER --kernel-trace -d <out>/COUNTER "
+                   "-o run -- python3 bench.py --steps 2 --warmup 1 --skip-cpu --skip-batched --calibrate-copy")
+TRAFFIC_KERNELS = [("gradient_laplacian", "k_tile<{t}, 7,"), ("divergence", "k_tile<{t}, 1,"),
+                   ("gradient_adjoint", "k_tile<{t}, 2,"), ("divergence_adjoint", "k_tile<{t}, 3,"),
+                   ("gradient", "k_tile<{t}, 0,"), ("laplacian", "k_tile<{t}, 4,"),
+                   ("divergence_curl", "k_tile<{t}, 8,"), ("remap_f640", "k_remap<{t},"),
+                   ("remap_adjoint_f640", "k_remap_adj<{t},")]
+TYPE_OF = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
+
+
+def _dispatches(db, counter=None):
+    """(short kernel name, duration ns or counter value) per dispatch of a
+    rocprofv3 database."""
+    import re
+    import sqlite3
+    c = sqlite3.connect(db)
+    short = lambda n: re.sub(r"^void ", "", re.sub(r"atlasnabla::\(anonymous namespace\)::", "", n))  # noqa: E731
+    if counter is None:
+        return [(short(n), e - s) for n, s, e in c.execute("select name, start, end from kernels")]
+    return [(short(n), v) for n, v in
+            c.execute("select kernel_name, value from counters_collection where counter_name = ?", (counter,))]
+
+
+def summarize_profiles(stats_db, fetch_db, write_db, stats_cmd, pmc_cmd):
+    """Writes profiles/bench_o1280x137_kernel_stats.md (kernel times) and
+    profiles/hbm_traffic.txt (HBM bytes per launch: the FETCH_SIZE and
+    WRITE_SIZE averages per kernel, in KiB, scaled so that the plain 4 GiB
+    device copy of --calibrate-copy reads 4 GiB fetched and written)."""
+    import collections
+    src = kernel_source_hash()
+    times = collections.defaultdict(list)
+    for n, d in _dispatches(stats_db):
+        times[n].append(d / 1e6)
+    total = sum(sum(v) for v in times.values())
+    rows = sorted(times.items(), key=lambda kv: -sum(kv[1]))
+    with open(os.path.join(ROOT, "profiles", "bench_o1280x137_kernel_stats.md"), "w") as fh:
+        fh.write("# Kernel time summary: bench O1280 x 137 (FP64, FP32, BF16 steps, remap, O640 batched)\n\n")
+        fh.write("Command (from the repository root, on one MI355X):\n\n```\n" + stats_cmd + "\n```\n\n")
+        fh.write(f"Kernel source hash (bench.kernel_source_hash): `{src}`.  The k_tile_batched rows include the "
+                 "autotuner's candidate shapes.\n\n")
+        fh.write("| kernel | calls | average ms | min ms | max ms | share % |\n|---|---|---|---|---|---|\n")
+        for n, v in rows:
+            if sum(v) / total < 0.002:
+                continue
+            fh.write(f"| `{n[:90]}` | {len(v)} | {sum(v) / len(v):.4f} | {min(v):.4f} | {max(v):.4f} | "
+                     f"{100 * sum(v) / total:.2f} |\n")
+    per, cal = {}, {}
+    for key, db in (("fetch", fetch_db), ("write", write_db)):
+        acc = collections.defaultdict(list)
+        for n, v in _dispatches(db, "FETCH_SIZE" if key == "fetch" else "WRITE_SIZE"):
+            acc[n].append(v)
+        per[key] = {n: sum(v) / len(v) for n, v in acc.items()}
+        # the calibration copy is the largest copyBuffer dispatch (4 GiB)
+        big = max(v for n, vs in acc.items() if n.startswith("__amd_rocclr_copyBuffer") for v in vs)
+        cal[key] = 4 * 2 ** 30 / (big * 1024)
+    cal_f, cal_w = cal["fetch"], cal["write"]
+    lines = ["# HBM traffic per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged per",
+             "# kernel), each scaled by what the same counter reads for a plain 4 GiB device copy (torch copy_ ->",
+             f"# __amd_rocclr_copyBuffer): FETCH x{cal_f:.3f}, WRITE x{cal_w:.3f}.",
+             "# Workload: bench.py O1280 x 137.  Commands (repository root, one MI355X):",
+             "#   " + pmc_cmd.replace("COUNTER", "FETCH_SIZE"), "#   " + pmc_cmd.replace("COUNTER", "WRITE_SIZE"),
+             "# Rows are valid only for the kernel source hash in column 1 (bench.py ignores others).",
+             "# hash op dtype fetch_bytes write_bytes"]
+    for dname, ty in TYPE_OF.items():
+        for op, pat in TRAFFIC_KERNELS:
+            pre = pat.format(t=ty)
+            names = [n for n in per["fetch"] if n.startswith(pre)]
+            if not names:
+                continue
+            n = max(names, key=lambda x: per["fetch"][x])   # the instance the bench times
+            if n not in per["write"]:
+                continue
+            lines.append(f"{src} {op} {dname} {per['fetch'][n] * 1024 * cal_f:.0f} {per['write'][n] * 1024 * cal_w:.0f}")
+        cons = [n for n in per["fetch"] if n.startswith(f"k_cons_partial<{ty},")]
+        if cons:
+            f_ = sum(per["fetch"][n] for n in cons[:1]) * 1024 * cal_f
+            w_ = sum(per["write"].get(n, 0.0) for n in cons[:1]) * 1024 * cal_w
+            lines.append(f"{src} conservation {dname} {f_:.0f} {w_:.0f}")
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,9 +630,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for rocprofv3 byte counters)")
     ap.add_argument("--cpu-leg", metavar="NPZ", help=argparse.SUPPRESS)   # the oracle child process
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write profiles/ summaries from rocprofv3 databases of this benchmark (no GPU needed)")
     args = ap.parse_args()
     if args.cpu_leg:
         print(json.dumps(cpu_leg(args.cpu_leg)))
+        return
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, PROFILE_STATS_CMD, PROFILE_PMC_CMD)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X and has no "
