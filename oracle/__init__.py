@@ -21,6 +21,9 @@ here in the readings listed in each module):
 * ``remap`` -- target grids (regular "F" and octahedral "O" Gaussian grids)
   and the linear interpolation of a field over the source triangles in 3-D
   on the sphere (Section 4.3, Figures 4-6), with brute-force point location.
+* ``capstudy`` -- alternative treatments of the poles for the accuracy study
+  only: pole-node fans on the spherical dual, and the dual taken in the
+  longitude-latitude plane with pole strips and antipodal pole edges.
 
 Everything is FP64 NumPy, vectorised where a loop would be too slow for the
 large grids; no blocking or reordering beyond what each formula states.
@@ -31,3 +34,4 @@ from .mesh import OMesh, build_mesh  # noqa: F401
 from .dual import DualGeometry, build_dual  # noqa: F401
 from . import nabla  # noqa: F401
 from . import remap  # noqa: F401
+from . import capstudy  # noqa: F401

@@ -92,18 +92,27 @@ def _canonical(tris):
     return rot[order]
 
 
-class OMesh:
-    """Connectivity of the triangulated O-grid; see the module docstring."""
+def band_triangles(grid):
+    """Zipper triangles of every band between consecutive rows (unoriented)."""
+    return np.concatenate([_band(grid, k) for k in range(grid.nrows - 1)], axis=0).astype(np.int64)
 
-    def __init__(self, grid):
+
+class OMesh:
+    """Connectivity of the triangulated O-grid; see the module docstring.
+
+    ``tris`` replaces the ladder-capped triangulation by another closed
+    triangulation of ``grid``'s nodes (any orientation; e.g. other polar
+    caps); such a mesh flags no pole edges."""
+
+    def __init__(self, grid, tris=None):
         self.grid = grid
         V = grid.nnodes
         self.nnodes = V
-        parts = [_cap(grid, 0)]
-        parts += [_band(grid, k) for k in range(grid.nrows - 1)]
-        parts.append(_cap(grid, grid.nrows - 1))
-        tris = np.concatenate(parts, axis=0).astype(np.int64)
-        tris = _orient_outward_ccw(grid.xyz, tris)
+        ladder = tris is None
+        if ladder:
+            parts = [_cap(grid, 0), band_triangles(grid), _cap(grid, grid.nrows - 1)]
+            tris = np.concatenate(parts, axis=0).astype(np.int64)
+        tris = _orient_outward_ccw(grid.xyz, np.asarray(tris, dtype=np.int64))
         self.tris = _canonical(tris)
         T = self.tris.shape[0]
         self.ntris = T
@@ -144,6 +153,9 @@ class OMesh:
         self.degree = np.diff(self.off)
 
         # pole edges: chords of the polar ladders
+        if not ladder:
+            self.is_pole = np.zeros(E, dtype=bool)
+            return
         ra = grid.node_row[a]
         rb = grid.node_row[b]
         polar = (ra == rb) & ((ra == 0) | (ra == grid.nrows - 1))
