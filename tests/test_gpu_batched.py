@@ -59,6 +59,24 @@ def test_batched_equals_single(dtype, mode):
     _check_against_single(M, tracers)
 
 
+@pytest.mark.parametrize("levels", [[1, 5, 19], [137], [2, 33, 1]], ids=["short", "one", "mixed"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batched_edge_plans(dtype, levels):
+    # plans of short columns only (tiles cut for 32 levels or fewer), a single
+    # tracer, and a short mix: persistent form and graph replay, bitwise
+    M = pa.Mesh("O16", device=0)
+    tracers = _tracers(M, levels, dtype, 5)
+    plan = pa.Batch(M, tracers)
+    for launch in (plan.run, plan.graph_launch, plan.graph_launch):
+        for tr in tracers:
+            for _, (x, y) in tr.items():
+                y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        _check_against_single(M, tracers)
+
+
 @pytest.mark.parametrize("mode", list(MODES))
 def test_graph_replays_equal_eager(mode):
     M = pa.Mesh("O32", device=0)
