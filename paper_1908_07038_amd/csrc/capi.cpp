@@ -715,10 +715,14 @@ struct atlas_remap_s {
   int32_t* adj_t = nullptr;   // [3P]
   void* adj_w64 = nullptr;    // [3P] FP64
   void* adj_w32 = nullptr;    // [3P] FP32
+  int32_t* head_t = nullptr;  // [V][2]: each node's first two entries (0 past its count)
+  void* head_w64 = nullptr;   // [V][2] FP64
+  void* head_w32 = nullptr;   // [V][2] FP32
   ~atlas_remap_s() {
     if (mesh && mesh->device >= 0) {
       DeviceGuard g(mesh->device);
-      for (void* p : {(void*)nodes, w64, w32, (void*)adj_off, (void*)adj_t, adj_w64, adj_w32})
+      for (void* p : {(void*)nodes, w64, w32, (void*)adj_off, (void*)adj_t, adj_w64, adj_w32, (void*)head_t, head_w64,
+                      head_w32})
         if (p) (void)hipFree(p);
     }
   }
@@ -765,6 +769,23 @@ int atlas_remap_build(atlas_mesh_t mesh, const char* target, atlas_remap_t* out)
         e = upload_to(r->host.adj_t.data(), r->host.adj_t.size() * sizeof(int32_t), reinterpret_cast<void**>(&r->adj_t));
       if (e == hipSuccess) e = upload_to(r->host.adj_w.data(), r->host.adj_w.size() * sizeof(double), &r->adj_w64);
       if (e == hipSuccess) e = upload_to(aw32.data(), aw32.size() * sizeof(float), &r->adj_w32);
+      {
+        // the first two entries of each node beside the compressed rows, so
+        // the transpose reads them with the row bounds, not after them
+        const RemapHost& h = r->host;
+        const int64_t V = mesh->host.V;
+        std::vector<int32_t> ht(2 * V, 0);
+        std::vector<double> hw(2 * V, 0.0);
+        for (int64_t n = 0; n < V; ++n)
+          for (int64_t q = 0; q < 2 && h.adj_off[n] + q < h.adj_off[n + 1]; ++q) {
+            ht[2 * n + q] = h.adj_t[h.adj_off[n] + q];
+            hw[2 * n + q] = h.adj_w[h.adj_off[n] + q];
+          }
+        const std::vector<float> hw32 = to_f32(hw);
+        if (e == hipSuccess) e = upload_to(ht.data(), ht.size() * sizeof(int32_t), reinterpret_cast<void**>(&r->head_t));
+        if (e == hipSuccess) e = upload_to(hw.data(), hw.size() * sizeof(double), &r->head_w64);
+        if (e == hipSuccess) e = upload_to(hw32.data(), hw32.size() * sizeof(float), &r->head_w32);
+      }
       if (e != hipSuccess) {
         (void)hipGetLastError();
         delete r;
@@ -841,8 +862,9 @@ int atlas_remap_apply_adjoint(atlas_remap_t remap, int dtype, int32_t nlev, cons
   DeviceGuard g(remap->mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
   const void* w = dtype == ATLAS_F64 ? remap->adj_w64 : remap->adj_w32;
-  hipError_t e = launch_remap_adjoint(dtype, remap->adj_off, remap->adj_t, w, remap->mesh->host.V, nlev, ybar, fbar,
-                                      (hipStream_t)stream);
+  const void* hw = dtype == ATLAS_F64 ? remap->head_w64 : remap->head_w32;
+  hipError_t e = launch_remap_adjoint(dtype, remap->adj_off, remap->adj_t, w, remap->head_t, hw, remap->mesh->host.V,
+                                      remap->host.P, nlev, ybar, fbar, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "remap adjoint");
   return ATLAS_OK;
 }

@@ -155,9 +155,12 @@ hipError_t scratch_address(int device, double** ptr);
 hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
                         void* out, hipStream_t stream);
 // Its transpose: out[n][k] = sum over e in [off[n], off[n+1]) of w[e] in[tt[e]][k]
-// for the V source nodes (off [V+1] int64, tt int32, w of the weight type).
-hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt, const void* w, int64_t V, int nlev,
-                                const void* in, void* out, hipStream_t stream);
+// for the V source nodes (off [V+1] int64, tt int32 < P, w of the weight type;
+// in is [P][nlev]); ht [V][2] and hw [V][2] repeat the first two entries of
+// each node (zero past its count).
+hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt, const void* w, const int32_t* ht,
+                                const void* hw, int64_t V, int64_t P, int nlev, const void* in, void* out,
+                                hipStream_t stream);
 
 // Batched persistent launch: one kernel over many fields (tracers) of one
 // operator on LDS tilings.  Per tracer: its fields, its tiling and records,

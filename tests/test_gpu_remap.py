@@ -6,9 +6,10 @@ Cases: the paper's O32 -> F8, an identity remap (O16 -> O16, every point on
 a node), a finer target (O12 -> F30), a target sharing the source's
 latitudes (O24 -> F24, points on edges and nodes) and a reduced target
 (O20 -> O9); levels 1, 10 (several points per wave), 33, 64, 65 and 137
-(one point per wave, ragged slices).  Bars as for the operators: FP64 1e-12,
+(one point per wave, ragged slices); the transpose also at 300 levels (a
+column in several blocks of levels).  Bars as for the operators: FP64 1e-12,
 FP32 1e-5 (total, against the FP64 input), BF16 4e-3 (against the oracle on
-the bf16-rounded input), normwise relative."""
+the bf16-rounded input), normwise and element-wise (also per level)."""
 import functools
 
 import numpy as np
@@ -19,6 +20,7 @@ import paper_1908_07038_amd as pa
 import workloads as W
 from oracle import remap as R
 from _oracle_cache import mesh_and_dual, coords
+from _parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -51,10 +53,6 @@ def _input(N, L, seed):
     return W.scaled_levels(s, L, 0.1) + W.normal((m.nnodes, L), seed + 1, 1e-3)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 CASES = [("O32", "F8"), ("O16", "O16"), ("O12", "F30"), ("O24", "F24"), ("O20", "O9"), ("O1", "F6")]
 
 
@@ -72,10 +70,7 @@ def test_remap_parity(src, dst, L, dtype):
     nodes, w = oracle_remap(src, dst)
     xin = xt.double().cpu().numpy() if dtype == torch.bfloat16 else x
     ref = R.apply(nodes, w, xin)
-    err = rel(y.double().cpu().numpy(), ref)
-    assert err <= TOL[dtype], (src, dst, L, dtype, err)
-    if dtype == torch.float64:
-        np.testing.assert_allclose(y.cpu().numpy(), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    check(y.double().cpu().numpy(), ref, TOL[dtype], ("remap", src, dst, L, str(dtype)), per_level=True)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
@@ -113,7 +108,7 @@ def test_remap_argument_errors():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
-@pytest.mark.parametrize("L", [1, 10, 65, 137])
+@pytest.mark.parametrize("L", [1, 10, 65, 137, 300])
 @pytest.mark.parametrize("src,dst", [("O32", "F8"), ("O12", "F30"), ("O24", "F24")])
 def test_remap_adjoint_parity(src, dst, L, dtype):
     """The transpose kernel against the oracle's scatter, and (FP64) the
@@ -125,8 +120,7 @@ def test_remap_adjoint_parity(src, dst, L, dtype):
     torch.cuda.synchronize()
     nodes, w = oracle_remap(src, dst)
     ref = R.apply_adjoint(nodes, w, y.double().cpu().numpy(), r.mesh.nnodes)
-    err = rel(fb.double().cpu().numpy(), ref)
-    assert err <= TOL[dtype], (src, dst, L, dtype, err)
+    check(fb.double().cpu().numpy(), ref, TOL[dtype], ("remap adjoint", src, dst, L, str(dtype)), per_level=True)
     if dtype == torch.float64:
         x = torch.from_numpy(_input(int(src[1:]), L, 60 + L)).to(DEV)
         rx = r(x)

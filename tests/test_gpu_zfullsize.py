@@ -4,6 +4,9 @@ hold at any size.
 
 * O640 and O1280 meshes: connectivity and indexing bit for bit, geometry to
   rounding, against the oracle's mesh.
+* Remap O1280 x 137 -> F640 and its transpose (FP64, FP32, BF16; the
+  transpose also at 164 levels in FP64, an input over 4 GiB) at sampled
+  target points / source nodes against the oracle's location.
 * O1280 x 137 (FP64, FP32, BF16 storage): every operator (and the curl) at ~700 sampled
   nodes (random, polar rows, nodes of degree 5 and 7, row starts, equator).
 * O320 x 137 (FP64, FP32): SH sum to degree 64 with scale 1 + 0.1 k plus
@@ -254,6 +257,89 @@ def test_o1280_to_f640_remap_sampled():
         del x, y
     ones = r(torch.ones((M.nnodes, 3), dtype=torch.float32, device=DEV))
     assert (ones - 1).abs().max().item() < 1e-6
+
+
+_REMAP = {}
+
+
+def o1280_f640():
+    """(GPU mesh, GPU remap) O1280 -> F640, built once per session."""
+    if not _REMAP:
+        M = pa.Mesh("O1280", radius=R, device=0)
+        _REMAP["r"] = (M, pa.Remap(M, "F640"))
+    return _REMAP["r"]
+
+
+def located_near(xyz, tris, first, targets, centre, rt, rtri):
+    """The oracle's location of the targets within angle rt of centre,
+    among the triangles whose first node is within rtri of it: (target
+    indices, nodes [n][3], weights [n][3])."""
+    from oracle import remap as Rm
+    t = np.nonzero(targets @ centre >= math.cos(rt))[0]
+    cand = np.nonzero(first @ centre >= math.cos(rtri))[0]
+    _, nodes, w = Rm.locate(xyz, tris[cand], targets[t])
+    return t, nodes, w
+
+
+@pytest.mark.parametrize("dtype,L", [(torch.float64, 137), (torch.float32, 137), (torch.bfloat16, 137),
+                                     (torch.float64, 164)], ids=["f64", "f32", "bf16", "f64-164"])
+def test_o1280_to_f640_remap_adjoint_sampled(dtype, L):
+    """Transpose of the O1280 -> F640 remap at ~160 sampled source nodes
+    (random, the two rows next to each pole, whose nodes take the most
+    target points, nodes of degree 5 and 7, the zero meridian) against the
+    oracle's location of every target point near each node: a target point
+    uses a node only if it lies in one of the node's triangles, within one
+    edge (at most 0.13 degrees on this mesh) of it, so the targets within
+    0.3 degrees (0.45 degrees of a pole for the polar rows) are all of them.
+    FP64 at 164 levels has an input over 4 GiB (the 64-bit addressing form).
+    Also the dot-product identity <R x, y> = <x, R^T y> over all nodes."""
+    from oracle import remap as Rm
+    print(f"O1280 <- F640 remap adjoint {dtype} L {L}", flush=True)
+    M, r = o1280_f640()
+    m, _ = oracle_mesh(1280)
+    g = m.grid
+    xyz, tris = g.xyz, m.tris
+    first = xyz[tris[:, 0]]
+    tg = Rm.TargetGrid("F640")
+    rng = np.random.default_rng(117 + L)
+    # every fifth node of the two rows next to each pole (44 nodes a pole)
+    polar = np.concatenate([np.arange(0, 44, 5), g.row_off[g.nrows - 2] + np.arange(0, 44, 5)])
+    other = np.unique(np.concatenate([rng.choice(M.nnodes, 100, replace=False), np.nonzero(m.degree != 6)[0],
+                                      g.row_off[np.arange(3, g.nrows - 3, 211)]]))
+    other = np.setdiff1d(other, polar)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(1170 + L)
+    y = torch.randn((r.npoints, L), generator=gen, device=DEV, dtype=torch.float64).to(dtype)
+    fb = r.adjoint(y)
+    torch.cuda.synchronize()
+    idx = np.concatenate([polar, other])
+    got = rows(fb, idx)
+    ref = np.zeros_like(got)
+    rad = math.radians
+    # the polar rows from one location per pole, the other nodes one by one
+    for i, n in enumerate(idx):
+        if i == 0 or i == polar.size // 2:
+            centre = np.array([0.0, 0.0, 1.0 if i == 0 else -1.0])
+            t, nodes, w = located_near(xyz, tris, first, tg.xyz, centre, rad(0.45), rad(0.8))
+            yt = rows(y, t)
+        elif i >= polar.size:
+            t, nodes, w = located_near(xyz, tris, first, tg.xyz, xyz[n], rad(0.3), rad(0.5))
+            yt = rows(y, t)
+        tr, slot = np.nonzero(nodes == n)
+        ref[i] = (w[tr, slot][:, None] * yt[tr]).sum(axis=0)
+    tol = {torch.float64: 1e-12, torch.float32: 1e-5, torch.bfloat16: 4e-3}[dtype]
+    err, emax = check(got, ref, tol, ("remap adjoint", str(dtype), L), per_level=True,
+                      groups={"polar rows": np.arange(polar.size)})
+    print(f"  remap adjoint {dtype} L {L}: rel L2 {err:.3e} max {emax:.3e}", flush=True)
+    if dtype == torch.float64:
+        gen.manual_seed(1180 + L)
+        x = torch.randn((M.nnodes, L), generator=gen, device=DEV, dtype=torch.float64)
+        rx = r(x)
+        lhs = float((rx * y).sum())
+        rhs = float((x * fb).sum())
+        assert abs(lhs - rhs) <= 1e-13 * float(rx.norm() * y.norm()), (lhs, rhs)
+        del x, rx
+    del y, fb
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
