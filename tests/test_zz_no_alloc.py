@@ -61,3 +61,32 @@ def test_noalloc_conservation_full_size_levels_and_limit():
     # the allocating call still takes it
     pa.conservation(M, big)
     torch.cuda.synchronize()
+
+
+def test_noalloc_conservation_replays_in_a_graph():
+    """Captured into a HIP graph (code under capture is what the call is for)
+    and replayed three times, with eager calls on the same static array and
+    synchronisations between the replays: every replay equals the eager
+    result bit for bit."""
+    M = pa.Mesh("O32", radius=6371220.0, device=0)
+    nlev = 64
+    d = pa.divergence(M, torch.from_numpy(W.normal((M.nnodes, nlev, 2), 44)).to(DEV))
+    other = pa.divergence(M, torch.from_numpy(W.normal((M.nnodes, 91, 2), 45)).to(DEV)).float()
+    s = torch.empty(nlev, dtype=torch.float64, device=DEV)
+    a = torch.empty(nlev, dtype=torch.float64, device=DEV)
+    pa.conservation_noalloc(M, d, s, a)        # eager: also sets up the array's address on this GPU
+    torch.cuda.synchronize()
+    s_ref, a_ref = s.clone(), a.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pa.conservation_noalloc(M, d, s, a)
+    so = torch.empty(91, dtype=torch.float64, device=DEV)
+    ao = torch.empty(91, dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        s.fill_(float("nan"))
+        a.fill_(float("nan"))
+        pa.conservation_noalloc(M, other, so, ao)   # other contents in the shared array
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(s, s_ref) and torch.equal(a, a_ref)
