@@ -108,7 +108,7 @@ def test_remap_argument_errors():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
-@pytest.mark.parametrize("L", [1, 10, 65, 137, 300])
+@pytest.mark.parametrize("L", [1, 10, 33, 65, 137, 300])
 @pytest.mark.parametrize("src,dst", [("O32", "F8"), ("O12", "F30"), ("O24", "F24")])
 def test_remap_adjoint_parity(src, dst, L, dtype):
     """The transpose kernel against the oracle's scatter, and (FP64) the
