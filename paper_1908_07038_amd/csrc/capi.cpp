@@ -842,7 +842,8 @@ int atlas_remap_apply(atlas_remap_t remap, int dtype, int32_t nlev, const void* 
   DeviceGuard g(remap->mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
   const void* w = dtype == ATLAS_F64 ? remap->w64 : remap->w32;
-  hipError_t e = launch_remap(dtype, remap->nodes, w, remap->host.P, nlev, src, dst, (hipStream_t)stream);
+  hipError_t e = launch_remap(dtype, remap->nodes, w, remap->mesh->host.V, remap->host.P, nlev, src, dst,
+                              (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "remap");
   return ATLAS_OK;
 }

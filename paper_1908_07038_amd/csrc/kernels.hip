@@ -1641,13 +1641,22 @@ __global__ __launch_bounds__(kTile2Threads<S>) void k_tile2(TileArgs a, int64_t 
 // the 4- and 2-byte types).  Blocks are remapped so that each XCD walks a
 // contiguous range of target points (whose source columns are neighbours, so
 // they stay in that XCD's L2).  The sum is w0 f0, then + w1 f1, then + w2 f2,
-// with fused multiply-adds.
-template <class S, int U, int TP>
+// with fused multiply-adds.  With O32 the input is addressed by 32-bit byte
+// offsets from its base (the launch checks that it is under 4 GiB); with
+// EXACT (64 lanes, U = the column's 64-level slices) every slice but the
+// last lies inside the column, at a constant offset from the first.
+template <class S, int U, int TP, bool O32 = false, bool EXACT = false>
 __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes, const void* __restrict__ wv,
                                                const S* __restrict__ in, S* __restrict__ out, int64_t P, int L,
                                                int lanes, int64_t nblocks, int remap) {
   using C = typename Traits<S>::C;
   const C* __restrict__ w = static_cast<const C*>(wv);
+  const char* __restrict__ inb = reinterpret_cast<const char*>(in);
+  const uint32_t colB = (uint32_t)L * (uint32_t)sizeof(S);
+  auto src = [&](int32_t node, int k) -> const S* {
+    if constexpr (O32) return reinterpret_cast<const S*>(inb + ((uint32_t)node * colB + (uint32_t)k * (uint32_t)sizeof(S)));
+    else return in + (size_t)node * (size_t)L + k;
+  };
   const int64_t lb = logical_block(blockIdx.x, nblocks, remap);
   if (lb >= nblocks) return;
   const int W = blockDim.x >> 6;
@@ -1673,11 +1682,17 @@ __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes
     for (int q = 0; q < TP; ++q)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + lanes * u;
-        const int kc = k < L ? k : L - 1;
-        v0[q][u] = ld1(in + (size_t)nd[q].x * (size_t)L + kc);
-        v1[q][u] = ld1(in + (size_t)nd[q].y * (size_t)L + kc);
-        v2[q][u] = ld1(in + (size_t)nd[q].z * (size_t)L + kc);
+        if (EXACT && u < U - 1) {
+          v0[q][u] = ld1(src(nd[q].x, k0) + 64 * u);
+          v1[q][u] = ld1(src(nd[q].y, k0) + 64 * u);
+          v2[q][u] = ld1(src(nd[q].z, k0) + 64 * u);
+        } else {
+          const int k = k0 + lanes * u;
+          const int kc = k < L ? k : L - 1;
+          v0[q][u] = ld1(src(nd[q].x, kc));
+          v1[q][u] = ld1(src(nd[q].y, kc));
+          v2[q][u] = ld1(src(nd[q].z, kc));
+        }
       }
 #pragma unroll
     for (int q = 0; q < TP; ++q)
@@ -1692,9 +1707,22 @@ __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes
   }
 }
 
+template <class S, int U, int TP>
+void launch_remap_u(dim3 g, dim3 b, hipStream_t st, const int32_t* nodes, const void* w, const S* src, S* dst,
+                    int64_t V, int64_t P, int nlev, int lanes, int64_t nblocks) {
+  const bool o32 = (uint64_t)V * (uint64_t)nlev * sizeof(S) < (1ull << 32);
+  const bool exact = lanes == 64 && (nlev + 63) / 64 == U;
+  if (o32 && exact)
+    hipLaunchKernelGGL((k_remap<S, U, TP, true, true>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1);
+  else if (o32)
+    hipLaunchKernelGGL((k_remap<S, U, TP, true, false>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1);
+  else
+    hipLaunchKernelGGL((k_remap<S, U, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1);
+}
+
 template <class S, int TP>
-hipError_t launch_remap_tp(const int32_t* nodes, const void* w, int64_t P, int nlev, const S* src, S* dst,
-                           hipStream_t st) {
+hipError_t launch_remap_tp(const int32_t* nodes, const void* w, int64_t V, int64_t P, int nlev, const S* src,
+                           S* dst, hipStream_t st) {
   const int lanes = nlev <= 32 ? nlev : 64;
   const int G = 64 / lanes;
   constexpr int W = 4;
@@ -1705,9 +1733,9 @@ hipError_t launch_remap_tp(const int32_t* nodes, const void* w, int64_t P, int n
   const int U = nsl < 3 ? nsl : 3;
   const dim3 g((unsigned)grid), b(64 * W);
   switch (U) {
-    case 1: hipLaunchKernelGGL((k_remap<S, 1, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
-    case 2: hipLaunchKernelGGL((k_remap<S, 2, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
-    default: hipLaunchKernelGGL((k_remap<S, 3, TP>), g, b, 0, st, nodes, w, src, dst, P, nlev, lanes, nblocks, 1); break;
+    case 1: launch_remap_u<S, 1, TP>(g, b, st, nodes, w, src, dst, V, P, nlev, lanes, nblocks); break;
+    case 2: launch_remap_u<S, 2, TP>(g, b, st, nodes, w, src, dst, V, P, nlev, lanes, nblocks); break;
+    default: launch_remap_u<S, 3, TP>(g, b, st, nodes, w, src, dst, V, P, nlev, lanes, nblocks); break;
   }
   return hipGetLastError();
 }
@@ -1715,13 +1743,13 @@ hipError_t launch_remap_tp(const int32_t* nodes, const void* w, int64_t P, int n
 // Target points per lane group (measured at O1280 x 137 -> F640): one for
 // FP64, two (columns of at most 32 levels) or four for 4- and 2-byte data.
 template <class S>
-hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in, void* out,
-                          hipStream_t st) {
+hipError_t launch_remap_t(const int32_t* nodes, const void* w, int64_t V, int64_t P, int nlev, const void* in,
+                          void* out, hipStream_t st) {
   const S* src = static_cast<const S*>(in);
   S* dst = static_cast<S*>(out);
-  if constexpr (sizeof(S) == 8) return launch_remap_tp<S, 1>(nodes, w, P, nlev, src, dst, st);
-  else if (nlev <= 32) return launch_remap_tp<S, 2>(nodes, w, P, nlev, src, dst, st);
-  else return launch_remap_tp<S, 4>(nodes, w, P, nlev, src, dst, st);
+  if constexpr (sizeof(S) == 8) return launch_remap_tp<S, 1>(nodes, w, V, P, nlev, src, dst, st);
+  else if (nlev <= 32) return launch_remap_tp<S, 2>(nodes, w, V, P, nlev, src, dst, st);
+  else return launch_remap_tp<S, 4>(nodes, w, V, P, nlev, src, dst, st);
 }
 
 // Transpose of the remapping: fbar[n][k] = the sum over the entries (t, w)
@@ -2709,13 +2737,13 @@ hipError_t launch_tiles_batched(int op, int dtype, const BatchTile* tr, const in
   }
 }
 
-hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
-                        void* out, hipStream_t stream) {
-  if (P < 1 || nlev < 1 || (P + 15) / 16 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t V, int64_t P, int nlev,
+                        const void* in, void* out, hipStream_t stream) {
+  if (V < 1 || P < 1 || nlev < 1 || (P + 15) / 16 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
   switch (dtype) {
-    case DT_F64: return launch_remap_t<double>(nodes, w, P, nlev, in, out, stream);
-    case DT_F32: return launch_remap_t<float>(nodes, w, P, nlev, in, out, stream);
-    case DT_BF16: return launch_remap_t<bf16_t>(nodes, w, P, nlev, in, out, stream);
+    case DT_F64: return launch_remap_t<double>(nodes, w, V, P, nlev, in, out, stream);
+    case DT_F32: return launch_remap_t<float>(nodes, w, V, P, nlev, in, out, stream);
+    case DT_BF16: return launch_remap_t<bf16_t>(nodes, w, V, P, nlev, in, out, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -150,10 +150,10 @@ constexpr int kMaxScratchDevices = 64;
 hipError_t scratch_address(int device, double** ptr);
 
 // Remapping: out[t][k] = sum_j w[t][j] in[nodes[t][j]][k] over P target
-// points; nodes [P][4] int32 and w [P][4] (FP64 for DT_F64, FP32 otherwise),
-// fourth entries unused.
-hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t P, int nlev, const void* in,
-                        void* out, hipStream_t stream);
+// points; nodes [P][4] int32 (< V) and w [P][4] (FP64 for DT_F64, FP32
+// otherwise), fourth entries unused; in is [V][nlev].
+hipError_t launch_remap(int dtype, const int32_t* nodes, const void* w, int64_t V, int64_t P, int nlev,
+                        const void* in, void* out, hipStream_t stream);
 // Its transpose: out[n][k] = sum over e in [off[n], off[n+1]) of w[e] in[tt[e]][k]
 // for the V source nodes (off [V+1] int64, tt int32 < P, w of the weight type;
 // in is [P][nlev]); ht [V][2] and hw [V][2] repeat the first two entries of
