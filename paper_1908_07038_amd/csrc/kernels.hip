@@ -52,12 +52,15 @@ template <> struct Traits<bf16_t> { using C = float; using C2 = float2; };
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
-// round to nearest even; NaN stays a (quiet) NaN
-__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+// FP32 to BF16, round to nearest even, a NaN kept as a quiet NaN with its
+// payload's top bits: gfx950's v_cvt_pk_bf16_f32, one instruction for two
+// values (checked equal, on all 2^32 inputs, to the rounding written out on
+// the bits: add 0x7fff plus the lowest kept bit, keep the top half).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float x, float y) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, y}, bf16x2_t));
 }
 
 __device__ __forceinline__ double ld1(const double* p) { return *p; }
@@ -74,7 +77,6 @@ __device__ __forceinline__ float2 ld2(const bf16_t* p) {
 // Output stores: plain, or non-temporal (streamed past L2) when the launch
 // asks for it.  Plain stores let L2 merge the partial cache lines shared by
 // the columns of neighbouring nodes.
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <bool NT, class T>
@@ -100,7 +102,7 @@ __device__ __forceinline__ void st2(float* p, float x, float y) {
 }
 template <bool NT>
 __device__ __forceinline__ void st2(bf16_t* p, float x, float y) {
-  st_raw<NT>(reinterpret_cast<uint32_t*>(p), f32_to_bf16(x) | (f32_to_bf16(y) << 16));
+  st_raw<NT>(reinterpret_cast<uint32_t*>(p), f32x2_to_bf16x2(x, y));
 }
 
 // Read-only table data read through the constant address space: with a
@@ -1694,15 +1696,25 @@ __global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ nodes
           v2[q][u] = ld1(src(nd[q].z, kc));
         }
       }
+    // every sum is formed before the guarded stores (keep), so the compiler
+    // cannot sink the loads of a partial last slice into the store's branch,
+    // where they would issue late and wait for all loads in flight
+    C r[TP][U];
 #pragma unroll
     for (int q = 0; q < TP; ++q)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         C acc = w0[q] * v0[q][u];
         acc = fma(w1[q], v1[q][u], acc);
-        acc = fma(w2[q], v2[q][u], acc);
+        r[q][u] = fma(w2[q], v2[q][u], acc);
+        keep(r[q][u]);
+      }
+#pragma unroll
+    for (int q = 0; q < TP; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
         const int k = k0 + lanes * u;
-        if (k < L && t0 + q < P) st1<false>(out + (size_t)(t0 + q) * (size_t)L + k, acc);
+        if (k < L && t0 + q < P) st1<false>(out + (size_t)(t0 + q) * (size_t)L + k, r[q][u]);
       }
   }
 }
@@ -2333,7 +2345,7 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   if (dtype == DT_F32)
     d = lap ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
   else if (dtype == DT_BF16)
-    d = lap ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 40, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+    d = lap ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 80, 4, 0, 0, 0, 16} : Def{3, 64, 4, 0, 0, 0, 16};
   else
     d = lap ? Def{3, 160, 4, 0, 0, 0, 16} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
