@@ -39,13 +39,17 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 GEOM_BYTES_PER_NODE = 104  # S_e (24 B) + two int32 ends (8 B) per edge x 3 edges, + V_i (8 B)
 METRIC = "edge-level updates/s and % HBM peak, Nabla grad+div+lap O1280×137, FP32 vs FP64"
 UNIT = "edge-level updates/s"
-OPS = ["gradient_laplacian", "divergence", "gradient_adjoint", "divergence_adjoint", "conservation"]
-SEPARATE = ["gradient", "laplacian"]   # timed alone as well (not in the step)
+# the step: gradient and Laplacian of f in one pass, divergence and gradient
+# adjoint of that gradient in one pass, divergence adjoint of the divergence,
+# conservation sums of the divergence
+OPS = ["gradient_laplacian", "divergence_gradient_adjoint", "divergence_adjoint", "conservation"]
+SEPARATE = ["gradient", "laplacian", "divergence", "gradient_adjoint"]   # timed alone as well (not in the step)
 # (elements read, elements written) per node-level, and edge sweeps
 OP_ELEMS = {"gradient": (1, 2), "divergence": (2, 1), "laplacian": (1, 1), "gradient_laplacian": (1, 3),
-            "gradient_adjoint": (2, 1), "divergence_adjoint": (1, 2), "conservation": (1, 0)}
+            "gradient_adjoint": (2, 1), "divergence_adjoint": (1, 2), "conservation": (1, 0),
+            "divergence_gradient_adjoint": (2, 2)}
 OP_SWEEPS = {"gradient": 1, "divergence": 1, "laplacian": 2, "gradient_laplacian": 3, "gradient_adjoint": 1,
-             "divergence_adjoint": 1, "conservation": 0}
+             "divergence_adjoint": 1, "conservation": 0, "divergence_gradient_adjoint": 2}
 CONSERVATION_KERNELS = "k_cons_partial + k_cons_final"
 
 
@@ -55,13 +59,9 @@ def kernel_names(pa, mesh, dtype_code, L):
             "gradient_adjoint": pa.OP_GRADIENT_ADJOINT, "divergence_adjoint": pa.OP_DIVERGENCE_ADJOINT}
     names = {op: pa.describe(mesh, b, dtype_code, L)[1] for op, b in bits.items()}
     names["conservation"] = CONSERVATION_KERNELS
-    # the one-pass gradient and Laplacian runs the Laplacian's one-tile shape
-    # with kernel operator 7; on any other shape it is the two calls
-    lap = names["laplacian"]
-    fused = lap.replace(", 4, ", ", 7, ")
-    if dtype_code == pa.F64 and fused.startswith("k_tile<"):   # one slice per step in FP64
-        fused = fused[:fused.rindex(",")] + ", 1>"
-    names["gradient_laplacian"] = fused if lap.startswith("k_tile<") else names["gradient"] + " + " + lap
+    # the one-pass calls: their kernel, or "two calls" when the shape is not the one-tile form
+    names["gradient_laplacian"] = pa.describe(mesh, pa.OP_GRADIENT_LAPLACIAN, dtype_code, L)[1]
+    names["divergence_gradient_adjoint"] = pa.describe(mesh, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, dtype_code, L)[1]
     return names
 
 
@@ -153,6 +153,7 @@ def run_gpu(args):
             "divergence": lambda: pa.divergence(mesh, g, out=d),
             "laplacian": lambda: pa.laplacian(mesh, f, out=lp),
             "gradient_adjoint": lambda: pa.gradient_adjoint(mesh, g, out=fT),
+            "divergence_gradient_adjoint": lambda: pa.divergence_gradient_adjoint(mesh, g, d, fT),
             "divergence_adjoint": lambda: pa.divergence_adjoint(mesh, d, out=gT),
             "conservation": lambda: pa.conservation(mesh, d),
         }
@@ -181,7 +182,8 @@ def run_gpu(args):
                           "hbm_frac": round(by / (ms * 1e-3) / HBM_PEAK, 3)}
             if OP_SWEEPS[op]:
                 per_op[op]["edge_updates_s"] = float(f"{OP_SWEEPS[op] * E * L / (ms * 1e-3):.4g}")
-        # the gradient and the Laplacian as separate calls (not in value)
+        # the gradient, the Laplacian, the divergence and the gradient adjoint
+        # as separate calls (not in value)
         for op in SEPARATE:
             calls[op]()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -538,6 +540,7 @@ PROFILE_PMC_CMD = ("cd /tmp && export TMPDIR=/tmp && cd <repo> && rocprofv3 --pm
                    "-o run -- python3 bench.py --steps 2 --warmup 1 --skip-cpu --skip-batched --calibrate-copy")
 TRAFFIC_KERNELS = [("gradient_laplacian", "k_tile<{t}, 7,"), ("divergence", "k_tile<{t}, 1,"),
                    ("gradient_adjoint", "k_tile<{t}, 2,"), ("divergence_adjoint", "k_tile<{t}, 3,"),
+                   ("divergence_gradient_adjoint", "k_tile<{t}, 8,"),
                    ("gradient", "k_tile<{t}, 0,"), ("laplacian", "k_tile<{t}, 4,"),
                    ("divergence_curl", "k_tile<{t}, 8,"), ("remap_f640", "k_remap<{t},"),
                    ("remap_adjoint_f640", "k_remap_adj<{t},")]
@@ -676,7 +679,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded SH degree 256 + level trend)",
         "config": {"workload": f"{args.grid} x {L} levels, FP32 fields, FP64 geometry: grad, div, fused lap, "
-                               "grad adjoint, div adjoint, FP64 conservation", "nnodes": V, "nedges": E,
+                               "grad adjoint, div adjoint, FP64 conservation (grad and lap of f in one pass, div "
+                               "and grad adjoint of that gradient in one pass)", "nnodes": V, "nedges": E,
                    "nlev": L, "edge_updates_per_step": 6 * E * L},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -198,6 +198,18 @@ int atlas_nabla_curl(atlas_mesh_t mesh, int dtype, int32_t nlev,
 int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev,
                                 const void* uv, void* div, void* zeta, void* stream);
 
+/* Divergence (Section 2.3) and gradient adjoint of one vector field in one
+ * pass, bitwise the values of atlas_nabla_divergence and
+ * atlas_nabla_gradient_adjoint (up to the sign of zero): both combine a
+ * node's own value and its 1-ring neighbours' values with one coefficient
+ * pair each, so the same loads feed both sums and the field is read from
+ * memory once.  uv: vector [V][nlev][2]; div, fbar: scalar [V][nlev]; no
+ * two of them may overlap.  One kernel on the divergence's launch shape
+ * when that is the one-tile LDS form (the default for columns of more than
+ * 32 levels), else the two calls one after the other. */
+int atlas_nabla_divergence_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
+                                            const void* uv, void* div, void* fbar, void* stream);
+
 /* Exact transpose of atlas_nabla_curl.
  * z: scalar [V][nlev] -> uvbar: vector [V][nlev][2]. */
 int atlas_nabla_curl_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev,
@@ -431,12 +443,25 @@ int atlas_nabla_tune(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
 int atlas_nabla_set_tune(atlas_mesh_t mesh, int dtype, uint32_t op,
                          const atlas_tune_t* tune);
 
+/* The one-pass calls, for atlas_nabla_describe only: the launches of
+ * atlas_nabla_gradient_laplacian (on the Laplacian's shape),
+ * atlas_nabla_divergence_curl and atlas_nabla_divergence_gradient_adjoint
+ * (on the divergence's). */
+enum {
+  ATLAS_OP_GRADIENT_LAPLACIAN = 1 << 16,
+  ATLAS_OP_DIVERGENCE_CURL = 1 << 17,
+  ATLAS_OP_DIVERGENCE_GRADIENT_ADJOINT = 1 << 18
+};
+
 /* Describe the launch a single-field call of (op, dtype) on nlev levels
  * would make with the mesh's current shape: the shape after per-operator
  * defaults are applied (to *resolved, if not NULL) and the name of the
  * kernel it runs, e.g. "k_tile<float, 0, 3>" (to kernel, NUL-terminated and
- * truncated to len bytes, if not NULL).  Works on host-only meshes; no
- * device work, no allocation. */
+ * truncated to len bytes, if not NULL).  op: one ATLAS_OP_* bit, or one of
+ * the one-pass codes above, whose kernel name reads "two calls" when the
+ * shape is not the one-tile LDS form (the call then runs its two operators
+ * one after the other; a BF16 field that is not 4-byte aligned does so too).
+ * Works on host-only meshes; no device work, no allocation. */
 int atlas_nabla_describe(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev,
                          atlas_tune_t* resolved, char* kernel, int32_t len);
 

@@ -28,6 +28,8 @@ LIB_PATH = os.path.join(_PKG, "lib", "libatlas_nabla.so")
 F64, F32, BF16 = 0, 1, 2
 OP_GRADIENT, OP_DIVERGENCE, OP_GRADIENT_ADJOINT, OP_DIVERGENCE_ADJOINT, OP_LAPLACIAN = 1, 2, 4, 8, 16
 OP_CURL, OP_CURL_ADJOINT = 32, 64
+# the one-pass calls, for describe() only
+OP_GRADIENT_LAPLACIAN, OP_DIVERGENCE_CURL, OP_DIVERGENCE_GRADIENT_ADJOINT = 1 << 16, 1 << 17, 1 << 18
 STATUS = {0: "ATLAS_OK", -1: "ATLAS_EINVAL", -2: "ATLAS_ENOMEM", -3: "ATLAS_EHIP",
           -4: "ATLAS_ENODEV", -5: "ATLAS_EDTYPE", -6: "ATLAS_ESHAPE"}
 
@@ -85,6 +87,7 @@ _SIGS = {
     "atlas_nabla_conservation_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_gradient_laplacian": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_divergence_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
+    "atlas_nabla_divergence_gradient_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P, _P]),
     "atlas_nabla_curl": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_nabla_curl_adjoint": (ctypes.c_int, [_P, ctypes.c_int, _I32, _P, _P, _P]),
     "atlas_batch_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(TracerDesc), _I32,
@@ -430,6 +433,26 @@ def divergence_curl(mesh, uv, out_div=None, out_curl=None):
     return out_div, out_curl
 
 
+def divergence_gradient_adjoint(mesh, uv, out_div=None, out_fbar=None):
+    """(divergence(uv), gradient_adjoint(uv)) in one pass over uv (same values
+    as the two calls, up to the sign of zero)."""
+    import torch
+    nlev = _field(mesh, uv, 2, "uv")
+    if out_div is not None:
+        _like(mesh, out_div, 1, nlev, uv.dtype, "out_div")
+    if out_fbar is not None:
+        _like(mesh, out_fbar, 1, nlev, uv.dtype, "out_fbar")
+    if out_div is None:
+        out_div = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+    if out_fbar is None:
+        out_fbar = torch.empty((mesh.nnodes, nlev), dtype=uv.dtype, device=uv.device)
+    _check(lib().atlas_nabla_divergence_gradient_adjoint(mesh.handle, _dtype_code(uv), nlev,
+                                                         ctypes.c_void_p(uv.data_ptr()),
+                                                         ctypes.c_void_p(out_div.data_ptr()),
+                                                         ctypes.c_void_p(out_fbar.data_ptr()), _stream(uv)))
+    return out_div, out_fbar
+
+
 def conservation(mesh, div):
     """Per-level FP64 (sum V_i div_ik, sum |V_i div_ik|) as device tensors."""
     import torch
@@ -471,7 +494,9 @@ def tune(mesh, op, x, out, reps=10):
 
 
 def describe(mesh, op, dtype_code, nlev):
-    """(resolved shape dict, kernel name) of a single-field call of op."""
+    """(resolved shape dict, kernel name) of a single-field call of op (an OP_*
+    bit, or OP_GRADIENT_LAPLACIAN, OP_DIVERGENCE_CURL,
+    OP_DIVERGENCE_GRADIENT_ADJOINT for the one-pass calls)."""
     sh = TuneShape()
     buf = ctypes.create_string_buffer(128)
     _check(lib().atlas_nabla_describe(mesh.handle, dtype_code, op, nlev, ctypes.byref(sh), buf, 128))

@@ -576,8 +576,14 @@ int atlas_nabla_gradient_laplacian(atlas_mesh_t mesh, int dtype, int32_t nlev, c
   return run_op(mesh, OP_LAP, dtype, nlev, f, lap, stream);
 }
 
-int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* div, void* zeta,
-                                void* stream) {
+namespace {
+
+// The divergence and a second divergence-form operator (op2: OP_CURL or
+// OP_GRADT) of one vector field: one pass of the dual kernel (fused op
+// OP_DIVCURL or OP_DIVGRADT) on the divergence's launch shape when that is
+// the one-tile LDS form, else the two operators one after the other.
+int divergence_pair(atlas_mesh_t mesh, int fused, int op2, const char* name, int dtype, int32_t nlev,
+                    const void* uv, void* div, void* out2, void* stream) {
   int rc = check_mesh_device(mesh);
   if (rc) return rc;
   const size_t es = dtype_size(dtype);
@@ -587,17 +593,16 @@ int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, cons
   if ((int64_t)nlev * V > (int64_t)UINT32_MAX) return fail(ATLAS_ESHAPE, "nnodes * nlev exceeds 2^32 - 1");
   if ((rc = check_field(uv, 2, es, "uv"))) return rc;
   if ((rc = check_field(div, 1, es, "div"))) return rc;
-  if ((rc = check_field(zeta, 1, es, "zeta"))) return rc;
+  if ((rc = check_field(out2, 1, es, op2 == OP_CURL ? "zeta" : "fbar"))) return rc;
   const size_t n1 = (size_t)V * nlev * es;
-  if (overlaps(uv, 2 * n1, div, n1) || overlaps(uv, 2 * n1, zeta, n1) || overlaps(div, n1, zeta, n1))
-    return fail(ATLAS_EINVAL, "uv, div and zeta must not overlap");
+  if (overlaps(uv, 2 * n1, div, n1) || overlaps(uv, 2 * n1, out2, n1) || overlaps(div, n1, out2, n1))
+    return fail(ATLAS_EINVAL, std::string("uv, div and ") + (op2 == OP_CURL ? "zeta" : "fbar") +
+                                  " must not overlap");
   DeviceGuard g(mesh->device);
   if (!g.ok) return fail(ATLAS_EHIP, "cannot select the mesh's device");
-  // one pass on the divergence's launch shape when that is the one-tile LDS
-  // form; otherwise the two operators run one after the other
-  const Shape sh = resolve_shape(OP_DIVCURL, dtype, nlev, mesh->shape[OP_DIV][dtype]);
+  const Shape sh = resolve_shape(fused, dtype, nlev, mesh->shape[OP_DIV][dtype]);
   TileGeom tg;
-  if (sh.lds_tiles == 3 && uses_tiles(OP_DIVCURL, dtype, nlev, sh)) tg = tile_geom(OP_DIVCURL, dtype, nlev, sh);
+  if (sh.lds_tiles == 3 && uses_tiles(fused, dtype, nlev, sh)) tg = tile_geom(fused, dtype, nlev, sh);
   if (dtype == ATLAS_BF16 && ((uintptr_t)uv & 3u)) tg.KL = 0;
   if (tg.KL > 0) {
     DevTiles dt;
@@ -606,18 +611,31 @@ int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, cons
       dt = mesh->tiles(tg, sh);
       dt.KL = tg.KL;
       dt.nchunks = tg.nchunks;
-      rec = mesh->tile_records(tg, sh, dt, OP_DIVCURL, dtype, (hipStream_t)stream);
+      rec = mesh->tile_records(tg, sh, dt, fused, dtype, (hipStream_t)stream);
     } catch (const std::bad_alloc&) {
       return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
     } catch (const std::exception& ex) {
       return fail(ATLAS_EHIP, ex.what());
     }
-    hipError_t e = launch_tiles(OP_DIVCURL, dtype, dt, rec, nlev, uv, div, sh, mesh->num_cus, (hipStream_t)stream, zeta);
-    if (e != hipSuccess) return hip_fail(e, "divergence_curl");
+    hipError_t e = launch_tiles(fused, dtype, dt, rec, nlev, uv, div, sh, mesh->num_cus, (hipStream_t)stream, out2);
+    if (e != hipSuccess) return hip_fail(e, name);
     return ATLAS_OK;
   }
   if ((rc = run_op(mesh, OP_DIV, dtype, nlev, uv, div, stream))) return rc;
-  return run_op(mesh, OP_CURL, dtype, nlev, uv, zeta, stream);
+  return run_op(mesh, op2, dtype, nlev, uv, out2, stream);
+}
+
+}  // namespace
+
+int atlas_nabla_divergence_curl(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* div, void* zeta,
+                                void* stream) {
+  return divergence_pair(mesh, OP_DIVCURL, OP_CURL, "divergence_curl", dtype, nlev, uv, div, zeta, stream);
+}
+
+int atlas_nabla_divergence_gradient_adjoint(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* uv, void* div,
+                                            void* fbar, void* stream) {
+  return divergence_pair(mesh, OP_DIVGRADT, OP_GRADT, "divergence_gradient_adjoint", dtype, nlev, uv, div, fbar,
+                         stream);
 }
 
 int atlas_nabla_conservation(atlas_mesh_t mesh, int dtype, int32_t nlev, const void* div, double* out_sum,
@@ -874,13 +892,25 @@ int atlas_nabla_describe(atlas_mesh_t mesh, int dtype, uint32_t op, int32_t nlev
                          int32_t len) {
   if (!mesh) return fail(ATLAS_EINVAL, "mesh is NULL");
   if (!dtype_size(dtype)) return fail(ATLAS_EDTYPE, "unknown dtype");
-  const int o = op_from_bit(op);
-  if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit");
+  // a one-pass call: its fused operator, on the shape entry it reads
+  const int fused = op == ATLAS_OP_GRADIENT_LAPLACIAN ? OP_GRADLAP
+                    : op == ATLAS_OP_DIVERGENCE_CURL ? OP_DIVCURL
+                    : op == ATLAS_OP_DIVERGENCE_GRADIENT_ADJOINT ? OP_DIVGRADT
+                                                                  : -1;
+  const int o = fused >= 0 ? (fused == OP_GRADLAP ? OP_LAP : OP_DIV) : op_from_bit(op);
+  if (o < 0) return fail(ATLAS_EINVAL, "op must be one ATLAS_OP_* bit or one-pass code");
   if (nlev <= 0) return fail(ATLAS_ESHAPE, "nlev must be >= 1");
   if (kernel && len <= 0) return fail(ATLAS_EINVAL, "len must be positive");
-  const Shape sh = resolve_shape(o, dtype, nlev, mesh->shape[o][dtype]);
+  const int k = fused >= 0 ? fused : o;
+  const Shape sh = resolve_shape(k, dtype, nlev, mesh->shape[o][dtype]);
   if (resolved) shape_out(sh, resolved);
-  if (kernel) kernel_label(o, dtype, nlev, sh, kernel, len);
+  if (kernel) {
+    // the one-pass calls run their kernel on the one-tile form only
+    if (fused >= 0 && !(sh.lds_tiles == 3 && uses_tiles(k, dtype, nlev, sh) && tile_geom(k, dtype, nlev, sh).KL > 0))
+      snprintf(kernel, (size_t)len, "two calls");
+    else
+      kernel_label(k, dtype, nlev, sh, kernel, len);
+  }
   return ATLAS_OK;
 }
 

@@ -624,7 +624,8 @@ struct TileArgs {
 };
 
 // Node record of the tile path: coefficient row (8 pairs, ring 1, followed
-// for OP_DIVCURL by the curl's 8 pairs; 24 weights, ring 2, followed for
+// for OP_DIVCURL by the 8 pairs of the second operator, the curl's or, for
+// OP_DIVGRADT, the gradient adjoint's; 24 weights, ring 2, followed for
 // OP_GRADLAP by the gradient's 8 pairs), LDS
 // position row (8 or 24 uint16), node index (int32), zero padding to 16
 // bytes.
@@ -634,7 +635,7 @@ struct TileRec {
   using C2 = typename Traits<S>::C2;
   static constexpr bool kRing2 = OP == OP_LAP || OP == OP_GRADLAP;
   static constexpr bool kGrad = OP == OP_GRADLAP;   // gradient pairs after the weights
-  static constexpr bool kDual = OP == OP_DIVCURL;    // curl pairs after the divergence pairs
+  static constexpr bool kDual = OP == OP_DIVCURL;    // second pairs after the divergence pairs
   static constexpr int kEntries = kRing2 ? kLapStride : 8;
   static constexpr uint32_t kLapB = kEntries * sizeof(C);   // ring 2: the 24 weights
   static constexpr uint32_t kCoefB = kRing2 ? kLapB + (kGrad ? 8 * sizeof(C2) : 0)
@@ -935,10 +936,11 @@ __device__ __forceinline__ void tile_node2g(const TileArgs& a, const char* lds, 
   for (int kb = 64 * U; kb < klc; kb += 64 * U) step(kb);
 }
 
-// One node of the divergence and the curl of one vector field (OP_DIVCURL):
+// One node of the divergence and a second operator of one vector field
+// (OP_DIVCURL: the curl, or the gradient adjoint on OP_DIVGRADT's records):
 // the same loads feed the divergence-form sums with the divergence pairs
-// (out) and with the curl pairs (out2), each exactly as tile_node1 computes
-// it for that operator.
+// (out) and with the second pairs (out2), each exactly as tile_node1
+// computes it for that operator.
 template <class S, int U, int DEG>
 __device__ __forceinline__ void tile_node1d(const TileArgs& a, const char* lds, const uint32_t* so, uint32_t xo,
                                             const typename Traits<S>::C2* cf, typename Traits<S>::C2 dg,
@@ -2339,15 +2341,24 @@ Shape resolve_shape(int op, int dtype, int nlev, const Shape& sh) {
   // (mode, KiB, tile rows, computing waves, copying waves, lanes per node,
   // waves per workgroup of the one-tile form)
   struct Def { int mode, kb, rows, cw, pw, lanes, wpb; };
-  const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL;
+  const bool vec_in = kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || kernel_op(op) == OP_DIVCURL;
   const bool lap = op == OP_LAP || op == OP_GRADLAP;   // the fused form takes the Laplacian's
+  // the divergence paired with the curl or the gradient adjoint in one pass
+  // (its records hold two coefficient rows)
+  const bool dual = kernel_op(op) == OP_DIVCURL;
   Def d;
   if (dtype == DT_F32)
-    d = lap ? Def{3, 80, 4, 0, 0, 0, 8} : vec_in ? Def{3, 64, 4, 0, 0, 0, 8} : Def{3, 40, 4, 0, 0, 0, 8};
+    d = lap    ? Def{3, 80, 4, 0, 0, 0, 8}
+        : dual ? Def{3, 80, 4, 0, 0, 0, 16}
+        : vec_in ? Def{3, 64, 4, 0, 0, 0, 8}
+                 : Def{3, 40, 4, 0, 0, 0, 8};
   else if (dtype == DT_BF16)
     d = lap ? Def{3, 53, 4, 0, 0, 0, 8} : vec_in ? Def{3, 80, 4, 0, 0, 0, 16} : Def{3, 64, 4, 0, 0, 0, 16};
   else
-    d = lap ? Def{3, 160, 4, 0, 0, 0, 16} : vec_in ? Def{3, 80, 4, 0, 0, 0, 8} : Def{3, 64, 3, 0, 0, 0, 8};
+    d = lap    ? Def{3, 160, 4, 0, 0, 0, 16}
+        : dual ? Def{3, 160, 4, 0, 0, 0, 8}
+        : vec_in ? Def{3, 80, 4, 0, 0, 0, 8}
+                 : Def{3, 64, 3, 0, 0, 0, 8};
   e.lds_tiles = d.mode;
   if (d.mode == 2) return e;
   if (!e.tile_kb) e.tile_kb = d.kb;
@@ -2372,7 +2383,7 @@ bool uses_tiles(int op, int dtype, int nlev, const Shape& sh) {
 TileGeom tile_geom(int op, int dtype, int nlev, const Shape& sh) {
   TileGeom g;
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || kernel_op(op) == OP_DIVCURL) ? 2 : 1;
   g.ring = (op == OP_LAP || op == OP_GRADLAP) ? 2 : 1;
   g.row_bytes = tile_record_bytes(op, dtype);
   g.budget = (int64_t)(sh.tile_kb > 0 ? sh.tile_kb : kDefaultTileKB) * 1024;
@@ -2443,7 +2454,7 @@ int tile_slices(int KL, const Shape& sh) {
 
 int64_t tile_tail_bytes(int op, int dtype, int KL, int nlev, int U) {
   const int64_t es = dtype == DT_F64 ? 8 : dtype == DT_BF16 ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || kernel_op(op) == OP_DIVCURL) ? 2 : 1;
   // a step reads 64 U levels (64 on the single-slice paths) from level 0 on:
   // past a chunk of k levels up to round_up(k, 64 U) - k levels
   const int64_t step = 64 * (int64_t)U;
@@ -2458,8 +2469,10 @@ int64_t tile_record_bytes(int op, int dtype) {
     case OP_LAP * 2 + 1: return TileRec<double, OP_LAP>::kBytes;
     case OP_GRADLAP * 2: return TileRec<float, OP_GRADLAP>::kBytes;
     case OP_GRADLAP * 2 + 1: return TileRec<double, OP_GRADLAP>::kBytes;
-    case OP_DIVCURL * 2: return TileRec<float, OP_DIVCURL>::kBytes;
-    case OP_DIVCURL * 2 + 1: return TileRec<double, OP_DIVCURL>::kBytes;
+    case OP_DIVCURL * 2:
+    case OP_DIVGRADT * 2: return TileRec<float, OP_DIVCURL>::kBytes;
+    case OP_DIVCURL * 2 + 1:
+    case OP_DIVGRADT * 2 + 1: return TileRec<double, OP_DIVCURL>::kBytes;
     default: return dtype == DT_F64 ? TileRec<double, OP_GRAD>::kBytes : TileRec<float, OP_GRAD>::kBytes;
   }
 }
@@ -2468,8 +2481,12 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
                              int64_t V, void* rec, hipStream_t stream) {
   const int64_t n = V * (tile_record_bytes(op, dtype) / 4);
   const dim3 g((unsigned)((n + 255) / 256)), b(256);
-  const void* coef = (op == OP_LAP || op == OP_GRADLAP) ? t.lap_w : op == OP_DIVCURL ? t.coef[OP_DIV] : t.coef[op];
-  const void* coef2 = op == OP_GRADLAP ? t.coef[OP_GRAD] : op == OP_DIVCURL ? t.coef[OP_CURL] : nullptr;
+  const bool dual = op == OP_DIVCURL || op == OP_DIVGRADT;   // divergence rows, then the second operator's
+  const void* coef = (op == OP_LAP || op == OP_GRADLAP) ? t.lap_w : dual ? t.coef[OP_DIV] : t.coef[op];
+  const void* coef2 = op == OP_GRADLAP ? t.coef[OP_GRAD]
+                      : op == OP_DIVCURL ? t.coef[OP_CURL]
+                      : op == OP_DIVGRADT ? t.coef[OP_GRADT]
+                                          : nullptr;
   uint32_t* r = static_cast<uint32_t*>(rec);
   const bool f64 = dtype == DT_F64;
   if (op == OP_LAP) {
@@ -2478,7 +2495,7 @@ hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_
   } else if (op == OP_GRADLAP) {
     if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
     else hipLaunchKernelGGL((k_pack_records<float, OP_GRADLAP>), g, b, 0, stream, order, coef, coef2, loc, V, r);
-  } else if (op == OP_DIVCURL) {
+  } else if (dual) {
     if (f64) hipLaunchKernelGGL((k_pack_records<double, OP_DIVCURL>), g, b, 0, stream, order, coef, coef2, loc, V, r);
     else hipLaunchKernelGGL((k_pack_records<float, OP_DIVCURL>), g, b, 0, stream, order, coef, coef2, loc, V, r);
   } else {
@@ -2493,7 +2510,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   // the tiling's LDS footprint must be the one the kernel lays out
   const bool bf = dtype == DT_BF16;
   const int64_t es = dtype == DT_F64 ? 8 : bf ? 2 : 4;
-  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || op == OP_DIVCURL) ? 2 : 1;
+  const int64_t cin = (kernel_op(op) == OP_DIV || kernel_op(op) == OP_GRADT || kernel_op(op) == OP_DIVCURL) ? 2 : 1;
   const int64_t row = tile_record_bytes(op, dtype);
   const int64_t colb = (int64_t)dt.KL * cin * es + (bf ? kBf16ColExtra : 0);
   const int U3 = tile_slices(dt.KL, shape);
@@ -2512,7 +2529,7 @@ hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, 
   a.in = in;
   a.out = out;
   a.out2 = out2;
-  const bool two = op == OP_GRADLAP || op == OP_DIVCURL;
+  const bool two = op == OP_GRADLAP || kernel_op(op) == OP_DIVCURL;
   if (two != (out2 != nullptr) || (two && shape.lds_tiles != 3))
     return hipErrorInvalidValue;   // the one-pass forms: one-tile workgroups, both outputs
   a.ntiles = dt.ntiles;

@@ -12,13 +12,20 @@ namespace atlasnabla {
 // tangential face vector).
 enum Op : int { OP_GRAD = 0, OP_DIV = 1, OP_GRADT = 2, OP_DIVT = 3, OP_LAP = 4, OP_CURL = 5, OP_CURLT = 6,
                 OP_COUNT = 7 };
-// Kernel template an operator runs with.
-inline int kernel_op(int op) { return op == OP_CURL ? OP_DIV : op == OP_CURLT ? OP_DIVT : op; }
 // Gradient and two-ring Laplacian of one field in one pass over LDS tiles
 // (one-tile form only): an internal kernel operator beyond the public ones.
 constexpr int OP_GRADLAP = OP_COUNT;
 // Divergence and curl of one vector field in one pass (one-tile form only).
 constexpr int OP_DIVCURL = OP_COUNT + 1;
+// Divergence and gradient adjoint of one vector field in one pass: the
+// OP_DIVCURL kernel on records holding the divergence and gradient-adjoint
+// coefficient rows (both operators combine a vector field's 1-ring values
+// with a diagonal and one pair per slot, in slot order).
+constexpr int OP_DIVGRADT = OP_COUNT + 2;
+// Kernel template an operator runs with.
+inline int kernel_op(int op) {
+  return op == OP_CURL ? OP_DIV : op == OP_CURLT ? OP_DIVT : op == OP_DIVGRADT ? OP_DIVCURL : op;
+}
 enum Dtype : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
 
 // Device tables of one mesh for one coefficient precision (FP64 for DT_F64,
@@ -125,7 +132,8 @@ int tile_slices(int KL, const Shape& sh);
 hipError_t pack_tile_records(int op, int dtype, const DevTables& t, const int32_t* order, const uint16_t* loc,
                              int64_t V, void* rec, hipStream_t stream);
 // out2: the gradient output of OP_GRADLAP (out: its Laplacian), the curl
-// output of OP_DIVCURL (out: its divergence), else NULL.
+// output of OP_DIVCURL and the gradient adjoint of OP_DIVGRADT (out: their
+// divergence), else NULL.
 hipError_t launch_tiles(int op, int dtype, const DevTiles& dt, const void* rec, int nlev, const void* in,
                         void* out, const Shape& shape, int num_cus, hipStream_t stream, void* out2 = nullptr);
 

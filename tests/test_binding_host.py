@@ -58,6 +58,8 @@ def test_outputs_and_workspace_are_checked(mesh):
         with pytest.raises(ValueError):
             pa.divergence_curl(mesh, uv, out_div=bad)
         with pytest.raises(ValueError):
+            pa.divergence_gradient_adjoint(mesh, uv, out_fbar=bad)
+        with pytest.raises(ValueError):
             pa.gradient_laplacian(mesh, f, out_lap=bad)
     for bad in bad_out_vector:
         with pytest.raises(ValueError):

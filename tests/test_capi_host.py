@@ -144,6 +144,33 @@ def test_describe_resolves_the_default_paths():
         pa.describe(M, pa.OP_GRADIENT, pa.F32, 0)
 
 
+def test_describe_names_the_one_pass_kernels():
+    """The one-pass calls run the fused tile kernels (operator 7: gradient and
+    Laplacian; 8: the divergence with the curl or the gradient adjoint) on
+    their own default shapes, and their two operators one after the other
+    when the shape is not the one-tile form."""
+    M = pa.Mesh("O8", device=-1)
+    cases = [(pa.OP_GRADIENT_LAPLACIAN, pa.F32, 137, "k_tile<float, 7, 2>"),
+             (pa.OP_DIVERGENCE_CURL, pa.F32, 137, "k_tile<float, 8, 2>"),
+             (pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 137, "k_tile<float, 8, 2>"),
+             # FP64: one slice per step for the gradient and Laplacian; the
+             # divergence pairs on whole columns (160 KiB tiles), two slices
+             (pa.OP_GRADIENT_LAPLACIAN, pa.F64, 137, "k_tile<double, 7, 1>"),
+             (pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F64, 137, "k_tile<double, 8, 2>"),
+             (pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.BF16, 137, "k_tile<unsigned short, 8, 2>"),
+             (pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 19, "two calls")]
+    for op, dt, L, name in cases:
+        assert pa.describe(M, op, dt, L)[1] == name, (op, dt, L)
+    shape = pa.describe(M, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 137)[0]
+    assert (shape["tile_kb"], shape["waves_per_block"]) == (80, 16)
+    # the pairs read the divergence's shape entry
+    pa.set_tune(M, pa.OP_DIVERGENCE, pa.F32, dict(lds_tiles=2))
+    assert pa.describe(M, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 137)[1] == "two calls"
+    pa.set_tune(M, pa.OP_DIVERGENCE, pa.F32, None)
+    with pytest.raises(pa.AtlasError):
+        pa.describe(M, pa.OP_GRADIENT_LAPLACIAN | pa.OP_DIVERGENCE_CURL, pa.F32, 137)
+
+
 def test_tuning_cache_applies_shapes(tmp_path):
     """A JSON cache of tuned shapes is read back and set on the mesh."""
     from paper_1908_07038_amd import tuning

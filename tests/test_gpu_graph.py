@@ -1,11 +1,12 @@
 """The benchmark's step captured into a HIP graph: once every tiling and
 record table a call needs has been built by an eager call, the single-field
 calls launch kernels only (no allocation, no copy, no memset), so the whole
-step - gradient and Laplacian in one pass, divergence, both adjoints and
-the allocation-free conservation sums, curl and the remap with its
-transpose - records into one graph.  The graph is replayed three times,
-with eager calls on other fields and synchronisations between the replays,
-and every replay must equal the eager results bit for bit."""
+step - gradient and Laplacian in one pass, divergence and gradient adjoint
+in one pass, the divergence adjoint and the allocation-free conservation
+sums, curl and the remap with its transpose - records into one graph.  The
+graph is replayed three times, with eager calls on other fields and
+synchronisations between the replays, and every replay must equal the eager
+results bit for bit."""
 import pytest
 import torch
 
@@ -36,8 +37,7 @@ def test_step_replays_in_a_graph(dtype):
 
     def step():
         pa.gradient_laplacian(M, f, g, lp)
-        pa.divergence(M, g, out=d)
-        pa.gradient_adjoint(M, g, out=fT)
+        pa.divergence_gradient_adjoint(M, g, d, fT)
         pa.divergence_adjoint(M, d, out=gT)
         pa.curl(M, g, out=z)
         pa.conservation_noalloc(M, d, s, a)

@@ -402,24 +402,23 @@ def test_gradient_laplacian_in_one_pass(dtype):
         pa.gradient_laplacian(M, x, g, g.view(-1)[:M.nnodes * 137].view(M.nnodes, 137))
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
-def test_divergence_curl_in_one_pass(dtype):
-    """Divergence and curl of one vector field in one pass give the two
-    calls' values (up to the sign of zero) at every level count and on the
-    divergence launch shapes it runs with."""
+def _divergence_pair_case(dtype, fused, second, name):
+    """The divergence and a second operator of one vector field in one pass
+    give the two calls' values (up to the sign of zero) at every level count
+    and on the divergence launch shapes it runs with."""
     M = gpu_mesh(32)
     codes = {torch.float64: pa.F64, torch.float32: pa.F32, torch.bfloat16: pa.BF16}
     shapes = [None, dict(lds_tiles=3, tile_kb=16), dict(lds_tiles=3, tile_levels=50, waves_per_block=4),
               dict(lds_tiles=3, tile_kb=24, slices_per_iter=1, band_rows=2), dict(lds_tiles=2)]
     for L in (137, 96, 70, 40, 19, 1):
-        print(f"case divergence_curl L {L} {dtype}", flush=True)
+        print(f"case {name} L {L} {dtype}", flush=True)
         uv = torch.from_numpy(_input(32, L, 2, 33)).to(DEV).to(dtype)
         for sh in shapes:
             pa.set_tune(M, pa.OP_DIVERGENCE, codes[dtype], sh)
             try:
-                d, z = pa.divergence_curl(M, uv)
+                d, z = fused(M, uv)
                 d0 = pa.divergence(M, uv)
-                z0 = pa.curl(M, uv)
+                z0 = second(M, uv)
                 torch.cuda.synchronize()
             finally:
                 pa.set_tune(M, pa.OP_DIVERGENCE, codes[dtype], None)
@@ -428,4 +427,18 @@ def test_divergence_curl_in_one_pass(dtype):
     uv = torch.from_numpy(_input(32, 137, 2, 34)).to(DEV).to(dtype)
     d = torch.empty((M.nnodes, 137), dtype=dtype, device=DEV)
     with pytest.raises(pa.AtlasError):
-        pa.divergence_curl(M, uv, d, d)
+        fused(M, uv, d, d)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_divergence_curl_in_one_pass(dtype):
+    """Divergence and curl of one vector field in one pass equal the two calls."""
+    _divergence_pair_case(dtype, pa.divergence_curl, pa.curl, "divergence_curl")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=["f64", "f32", "bf16"])
+def test_divergence_gradient_adjoint_in_one_pass(dtype):
+    """Divergence and gradient adjoint of one vector field in one pass equal
+    the two calls (whose parity with the oracle is tested above)."""
+    _divergence_pair_case(dtype, pa.divergence_gradient_adjoint, pa.gradient_adjoint,
+                          "divergence_gradient_adjoint")

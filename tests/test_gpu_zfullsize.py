@@ -129,7 +129,10 @@ def test_o1280_sampled_parity():
         d, z = pa.divergence_curl(M, uv)
         assert torch.equal(d + 0.0, pa.divergence(M, uv) + 0.0)
         assert torch.equal(z + 0.0, pa.curl(M, uv) + 0.0)
-        del d, z, f, uv
+        d, fb = pa.divergence_gradient_adjoint(M, uv, d, z)
+        assert torch.equal(d + 0.0, pa.divergence(M, uv) + 0.0)
+        assert torch.equal(fb + 0.0, pa.gradient_adjoint(M, uv) + 0.0)
+        del d, z, fb, f, uv
         torch.cuda.empty_cache()
     print("  one-pass pairs equal to the separate calls", flush=True)
     # invariants at full size
