@@ -513,5 +513,6 @@ def set_tune(mesh, op, dtype_code, shape=None):
 
 
 from .autograd import (Gradient, Divergence, Laplacian, Curl, GradientLaplacian, DivergenceCurl,  # noqa: E402,F401
-                       RemapFunction, grad, div, lap, rot, grad_lap, div_rot, remap)
+                       DivergenceGradientAdjoint, RemapFunction, grad, div, lap, rot, grad_lap, div_rot, div_gradt,
+                       remap)
 from .batch import Batch  # noqa: E402,F401

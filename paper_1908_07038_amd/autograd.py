@@ -8,8 +8,8 @@ Laplacian L = D G has the adjoint G^T D^T.
 
 import torch
 
-from . import (curl, curl_adjoint, divergence, divergence_adjoint, divergence_curl, gradient, gradient_adjoint,
-               gradient_laplacian, laplacian)
+from . import (curl, curl_adjoint, divergence, divergence_adjoint, divergence_curl, divergence_gradient_adjoint,
+               gradient, gradient_adjoint, gradient_laplacian, laplacian)
 
 
 class Gradient(torch.autograd.Function):
@@ -92,6 +92,26 @@ class DivergenceCurl(torch.autograd.Function):
         return None, out
 
 
+class DivergenceGradientAdjoint(torch.autograd.Function):
+    """(div uv, G^T uv) in one pass; backward D^T dbar + G fbar_bar (the
+    gradient is the adjoint of the gradient adjoint)."""
+
+    @staticmethod
+    def forward(ctx, mesh, uv):
+        ctx.mesh = mesh
+        return divergence_gradient_adjoint(mesh, uv.contiguous())
+
+    @staticmethod
+    def backward(ctx, dbar, fbar):
+        out = None
+        if dbar is not None:
+            out = divergence_adjoint(ctx.mesh, dbar.contiguous())
+        if fbar is not None:
+            t = gradient(ctx.mesh, fbar.contiguous())
+            out = t if out is None else out + t
+        return None, out
+
+
 class RemapFunction(torch.autograd.Function):
     """Remap of a node field (see Remap); backward the exact transpose."""
 
@@ -130,6 +150,11 @@ def grad_lap(mesh, f):
 def div_rot(mesh, uv):
     """Differentiable (divergence, curl) of one vector field in one pass."""
     return DivergenceCurl.apply(mesh, uv)
+
+
+def div_gradt(mesh, uv):
+    """Differentiable (divergence, gradient adjoint) of one vector field in one pass."""
+    return DivergenceGradientAdjoint.apply(mesh, uv)
 
 
 def remap(r, f):

@@ -245,6 +245,8 @@ def test_autograd_gradcheck():
     assert torch.autograd.gradcheck(lambda t: pa.grad_lap(M, t)[1], (f,), eps=1e-6, atol=1e-6)
     assert torch.autograd.gradcheck(lambda t: pa.div_rot(M, t), (uv,), eps=1e-6, atol=1e-7)
     assert torch.autograd.gradcheck(lambda t: pa.div_rot(M, t)[0], (uv,), eps=1e-6, atol=1e-7)
+    assert torch.autograd.gradcheck(lambda t: pa.div_gradt(M, t), (uv,), eps=1e-6, atol=1e-7)
+    assert torch.autograd.gradcheck(lambda t: pa.div_gradt(M, t)[1], (uv,), eps=1e-6, atol=1e-7)
 
 
 def test_curl_of_solid_body_rotation():
