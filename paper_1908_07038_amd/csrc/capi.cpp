@@ -1077,6 +1077,7 @@ struct atlas_batch_s {
   Shape shape[4];           // launch shape of each operator
   std::vector<atlas_tracer_desc_t> descs;
   BatchOp ops[4];
+  BatchOp pair;             // divergence and gradient adjoint in one launch (see plan_pairs)
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1088,12 +1089,14 @@ struct atlas_batch_s {
     graph = nullptr;
   }
   void release_tables() {
-    for (BatchOp& bo : ops) {
+    auto release = [](BatchOp& bo) {
       if (bo.tr) (void)hipFree(bo.tr);
       if (bo.pre) (void)hipFree(bo.pre);
       if (bo.ctr) (void)hipFree(bo.ctr);
       bo = BatchOp();
-    }
+    };
+    for (BatchOp& bo : ops) release(bo);
+    release(pair);
   }
   ~atlas_batch_s() {
     if (!mesh) return;
@@ -1124,12 +1127,15 @@ int bucket_levels(int L, int Lmax) {
 // tracer's chunk (at most its tiling's) and slices, the per-XCD item counts,
 // the LDS size (largest tile plus read-past tail over the tracers) and the
 // grid (as many workgroups as the CUs hold at once).  Leaves bo.tiled false
-// when some tracer's tiles do not fit.
-int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
+// when some tracer's tiles do not fit.  pair: the divergence (o = OP_DIV)
+// with the gradient adjoint of the same fields in one pass (OP_DIVGRADT), on
+// the divergence's shape.
+int plan_op(atlas_batch_s* b, int o, BatchOp& bo, bool pair = false) {
+  const int k = pair ? OP_DIVGRADT : o;   // the launch's operator
   int Lmax = 1;
   for (const atlas_tracer_desc_t& d : b->descs) Lmax = std::max(Lmax, d.nlev);
   // tile defaults of the long-column launch, also for batches of short columns
-  const Shape sh = resolve_shape(o, b->dtype, std::max(Lmax, 33), b->shape[o]);
+  const Shape sh = resolve_shape(k, b->dtype, std::max(Lmax, 33), b->shape[o]);
   if (sh.lds_tiles != 3) return ATLAS_OK;
   const int ntr = (int)b->descs.size();
   std::map<int, std::pair<DevTiles, const void*>> tilings;
@@ -1142,13 +1148,13 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
     const int Lb = bucket_levels(d.L, Lmax);
     auto it = tilings.find(Lb);
     if (it == tilings.end()) {
-      const TileGeom tg = tile_geom(o, b->dtype, Lb, sh);
+      const TileGeom tg = tile_geom(k, b->dtype, Lb, sh);
       if (tg.KL < 1) return ATLAS_OK;
       try {
         DevTiles dt = b->mesh->tiles(tg, sh);
         dt.KL = tg.KL;
         dt.nchunks = tg.nchunks;
-        const void* rec = b->mesh->tile_records(tg, sh, dt, o, b->dtype, nullptr);
+        const void* rec = b->mesh->tile_records(tg, sh, dt, k, b->dtype, nullptr);
         it = tilings.emplace(Lb, std::make_pair(dt, rec)).first;
       } catch (const std::bad_alloc&) {
         return fail(ATLAS_ENOMEM, "cannot allocate the LDS tiles");
@@ -1159,6 +1165,7 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
     const DevTiles& dt = it->second.first;
     d.in = b->descs[t].in[o];
     d.out = b->descs[t].out[o];
+    d.out2 = pair ? b->descs[t].out[OP_GRADT] : nullptr;
     d.info = dt.info;
     d.segs = dt.segs;
     d.rec = static_cast<const char*>(it->second.second);
@@ -1167,7 +1174,7 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
     d.U = tile_slices(d.KL, sh);
     bo.umax = std::max(bo.umax, d.U);
     d.nitems = dt.ntiles * d.nchunks;
-    lds = std::max(lds, (int64_t)dt.lds_bytes + tile_tail_bytes(o, b->dtype, d.KL, d.L, d.U));
+    lds = std::max(lds, (int64_t)dt.lds_bytes + tile_tail_bytes(k, b->dtype, d.KL, d.L, d.U));
     for (int x = 0; x < 8; ++x) {
       const int64_t share = (x + 1) * d.nitems / 8 - x * d.nitems / 8;
       const int64_t next = (int64_t)pre[x * (ntr + 1) + t] + share;
@@ -1177,7 +1184,7 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
   }
   bo.waves = sh.waves_per_block;
   bo.claim = sh.batch_claim > 0 ? sh.batch_claim : kDefaultBatchClaim;
-  const int n = lds <= (int64_t)160 * 1024 ? tiles_batched_per_cu(o, b->dtype, (uint32_t)lds, bo.waves, bo.umax) : 0;
+  const int n = lds <= (int64_t)160 * 1024 ? tiles_batched_per_cu(k, b->dtype, (uint32_t)lds, bo.waves, bo.umax) : 0;
   if (n < 1) return ATLAS_OK;   // does not launch with this shape: field launches
   const int per_cu = sh.tile_wgs_per_cu > 0 ? std::min(sh.tile_wgs_per_cu, n) : n;
   bo.grid = std::max<int64_t>(8, (int64_t)per_cu * b->mesh->num_cus / 8 * 8);
@@ -1207,12 +1214,41 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo) {
   return ATLAS_OK;
 }
 
+// Whether the plan's divergence and gradient adjoint can run as one pass:
+// both asked for, on the same input field in every tracer, and no output of
+// either overlapping an input of any tracer (run one after the other, the
+// divergence of every tracer precedes every gradient adjoint; in one pass
+// they interleave).
+bool plan_pairs(const atlas_batch_s* b) {
+  // FP32 plans only: the FP64 pair of more than one slice per step does not
+  // fit the batched kernel's 128 registers
+  if (b->dtype != ATLAS_F32) return false;
+  if ((b->mask & ((1u << OP_DIV) | (1u << OP_GRADT))) != ((1u << OP_DIV) | (1u << OP_GRADT))) return false;
+  const size_t es = dtype_size(b->dtype);
+  const int64_t V = b->mesh->host.V;
+  for (const atlas_tracer_desc_t& d : b->descs)
+    if (d.in[OP_DIV] != d.in[OP_GRADT]) return false;
+  for (const atlas_tracer_desc_t& d : b->descs)
+    for (const atlas_tracer_desc_t& e : b->descs) {
+      const size_t nd = (size_t)V * d.nlev * es, ne = (size_t)V * e.nlev * es;
+      if (overlaps(d.out[OP_DIV], nd, e.in[OP_DIV], 2 * ne) || overlaps(d.out[OP_GRADT], nd, e.in[OP_DIV], 2 * ne))
+        return false;
+    }
+  return true;
+}
+
 // (Re)build the device work tables of a plan for its operators' shapes.
 int plan_upload(atlas_batch_s* b) {
   b->release_tables();
   for (int o = 0; o < 4; ++o) {
     if (!(b->mask & (1u << o)) || !plan_persistent(b->shape[o])) continue;
     int rc = plan_op(b, o, b->ops[o]);
+    if (rc) return rc;
+  }
+  // the divergence and the gradient adjoint of the same fields in one
+  // persistent launch, on the divergence's shape, where it fits
+  if (plan_persistent(b->shape[OP_DIV]) && plan_pairs(b)) {
+    int rc = plan_op(b, OP_DIV, b->pair, true);
     if (rc) return rc;
   }
   return ATLAS_OK;
@@ -1234,10 +1270,19 @@ int plan_run_op(atlas_batch_s* b, int o, hipStream_t st) {
   return ATLAS_OK;
 }
 
-// Operators outermost, in the order of their bits.
+// Operators outermost, in the order of their bits; the divergence and
+// gradient adjoint pair, where planned, in the divergence's place.
 int plan_run(atlas_batch_s* b, hipStream_t st) {
   for (int o = 0; o < 4; ++o) {
     if (!(b->mask & (1u << o))) continue;
+    if (b->pair.tiled && (o == OP_DIV || o == OP_GRADT)) {
+      if (o == OP_GRADT) continue;
+      const BatchOp& bo = b->pair;
+      hipError_t e = launch_tiles_batched(OP_DIVGRADT, b->dtype, bo.tr, bo.pre, (int)b->descs.size(), bo.ctr, bo.claim,
+                                          bo.lds, bo.waves, bo.grid, bo.umax, st);
+      if (e != hipSuccess) return hip_fail(e, "divergence_gradient_adjoint");
+      continue;
+    }
     int rc = plan_run_op(b, o, st);
     if (rc) return rc;
   }
@@ -1247,7 +1292,8 @@ int plan_run(atlas_batch_s* b, hipStream_t st) {
 // Whether every operator of the plan runs as one persistent launch.
 bool plan_all_tiled(const atlas_batch_s* b) {
   for (int o = 0; o < 4; ++o)
-    if ((b->mask & (1u << o)) && !b->ops[o].tiled) return false;
+    if ((b->mask & (1u << o)) && !b->ops[o].tiled && !(b->pair.tiled && (o == OP_DIV || o == OP_GRADT)))
+      return false;
   return true;
 }
 

@@ -1368,6 +1368,7 @@ __global__ __launch_bounds__(1024) void k_tile_batched(TileArgs base, const Batc
       const BatchTile* d = tr + t;
       a.in = global_ptr<const S>(&d->in);
       a.out = global_ptr<S>(&d->out);
+      if constexpr (OP == OP_DIVCURL) a.out2 = global_ptr<S>(&d->out2);
       a.info = reinterpret_cast<const int32_t*>(ld_const(reinterpret_cast<const uint64_t*>(&d->info)));
       a.segs = reinterpret_cast<const int32_t*>(ld_const(reinterpret_cast<const uint64_t*>(&d->segs)));
       a.rec = reinterpret_cast<const char*>(ld_const(reinterpret_cast<const uint64_t*>(&d->rec)));
@@ -2696,6 +2697,9 @@ const void* tb_fn(int op, int umax) {
     case OP_DIV: return tb_fn_u<S, OP_DIV>(umax);
     case OP_GRADT: return tb_fn_u<S, OP_GRADT>(umax);
     case OP_DIVT: return tb_fn_u<S, OP_DIVT>(umax);
+    case OP_DIVCURL:   // FP32 only (FP64 pairs exceed 128 registers)
+      if constexpr (std::is_same<S, float>::value) return tb_fn_u<S, OP_DIVCURL>(umax);
+      else return nullptr;
     default: return nullptr;
   }
 }
@@ -2718,6 +2722,10 @@ hipError_t launch_tb_t(int op, const TileArgs& a, const BatchTile* tr, const int
     case OP_DIV: return launch_tb_u<S, OP_DIV>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
     case OP_GRADT: return launch_tb_u<S, OP_GRADT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
     case OP_DIVT: return launch_tb_u<S, OP_DIVT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+    case OP_DIVCURL:
+      if constexpr (std::is_same<S, float>::value)
+        return launch_tb_u<S, OP_DIVCURL>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
+      else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -2744,7 +2752,10 @@ hipError_t launch_tiles_batched(int op, int dtype, const BatchTile* tr, const in
                                 int32_t claim, uint32_t lds, int waves, int64_t grid, int umax,
                                 hipStream_t stream) {
   const int kop = kernel_op(op);
-  if (kop != OP_GRAD && kop != OP_DIV && kop != OP_GRADT && kop != OP_DIVT) return hipErrorInvalidValue;
+  // the four batchable operators and, in FP32, the divergence and gradient
+  // adjoint pair (each tracer's out2 set)
+  if (kop != OP_GRAD && kop != OP_DIV && kop != OP_GRADT && kop != OP_DIVT && !(op == OP_DIVGRADT && dtype == DT_F32))
+    return hipErrorInvalidValue;
   // the grid is a multiple of 8 workgroups (one share per XCD)
   if (ntr < 1 || !ctr || claim < 1 || claim > 64 || grid < 8 || grid % 8 != 0 || grid > INT32_MAX || waves < 1 ||
       waves > 16 || lds > kLdsPerCu || umax < 1 || umax > 3)

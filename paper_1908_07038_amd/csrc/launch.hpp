@@ -177,6 +177,7 @@ hipError_t launch_remap_adjoint(int dtype, const int64_t* off, const int32_t* tt
 struct BatchTile {
   const void* in;
   void* out;
+  void* out2;            // the gradient adjoint of a divergence pair (OP_DIVGRADT), else NULL
   const int32_t* info;   // the tracer's tiling (DevTiles::info, segs) and its node records
   const int32_t* segs;
   const char* rec;

@@ -95,6 +95,33 @@ def test_graph_replays_equal_eager(mode):
         tracers[0]["gradient"][0].mul_(2.0)
 
 
+def _shared_tracers(mesh, levels, seed):
+    """Tracers whose divergence and gradient adjoint take the same vector
+    field (the plan runs them as one pass), the rest as in _tracers."""
+    tracers = _tracers(mesh, levels, torch.float32, seed)
+    for tr in tracers:
+        tr["gradient_adjoint"] = (tr["divergence"][0], tr["gradient_adjoint"][1])
+    return tracers
+
+
+@pytest.mark.parametrize("mode", ["persistent", "persistent_shaped", "persistent_claim8", "fields"])
+def test_batched_divergence_gradient_adjoint_pairs(mode):
+    # FP32 plans whose divergence and gradient adjoint read the same fields:
+    # one persistent launch for both (or the field launches), eager and
+    # replayed, bitwise the single-field calls
+    M = pa.Mesh("O32", device=0)
+    tracers = _shared_tracers(M, [1, 19, 60, 91, 137, 137, 5, 33, 2, 64], 11)
+    plan = pa.Batch(M, tracers, tune=MODES[mode])
+    for launch in (plan.run, plan.graph_launch, plan.graph_launch):
+        for tr in tracers:
+            for _, (x, y) in tr.items():
+                y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        _check_against_single(M, tracers)
+
+
 def test_batch_tune_keeps_results():
     M = pa.Mesh("O16", device=0)
     tracers = _tracers(M, [137, 19, 1], torch.float32, 3)
