@@ -360,13 +360,19 @@ def run_batched(args):
              for op, sh in shapes.items()}
     log(f"batched: tuned in {time.time() - t0:.1f}s ({tune_ms:.2f} ms): {tuned}")
     t_graph = time_graph(plan)
-    a.record()
-    for _ in range(reps):
+
+    def single_field():
         for tr in tracers:
             pa.gradient(mesh, tr["gradient"][0], out=tr["gradient"][1])
             # the divergence and gradient adjoint of g in one pass, as the plan runs them
             pa.divergence_gradient_adjoint(mesh, tr["divergence"][0], tr["divergence"][1], tr["gradient_adjoint"][1])
             pa.divergence_adjoint(mesh, tr["divergence_adjoint"][0], out=tr["divergence_adjoint"][1])
+
+    single_field()   # builds the one-pass calls' tilings and records outside the timed loop
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        single_field()
     b.record()
     torch.cuda.synchronize()
     t_single = a.elapsed_time(b) / reps
