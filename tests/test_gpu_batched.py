@@ -122,6 +122,24 @@ def test_batched_divergence_gradient_adjoint_pairs(mode):
         _check_against_single(M, tracers)
 
 
+def test_batched_pairs_after_tune():
+    # the autotuner times the divergence and the gradient adjoint one at a
+    # time and leaves the plan re-planned with the pair: still bitwise
+    M = pa.Mesh("O16", device=0)
+    tracers = _shared_tracers(M, [137, 19, 1, 60], 12)
+    plan = pa.Batch(M, tracers)
+    shapes, ms = plan.tune(reps=1)
+    assert ms > 0 and set(shapes) == set(COMPS)
+    for launch in (plan.run, plan.graph_launch, plan.graph_launch):
+        for tr in tracers:
+            for _, (x, y) in tr.items():
+                y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        _check_against_single(M, tracers)
+
+
 def test_batch_tune_keeps_results():
     M = pa.Mesh("O16", device=0)
     tracers = _tracers(M, [137, 19, 1], torch.float32, 3)
