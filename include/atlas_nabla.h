@@ -5,7 +5,7 @@
  * Atlas report (Section 2.3, Figure 2): a mesh is built once from a grid
  * name, fields are plain device arrays laid out as NodeColumns (one column of
  * levels per mesh node), and the Nabla operators the report lists among the
- * operations Atlas supplies (gradient, divergence, Laplacian; Section 2.3)
+ * operations the library offers (gradient, divergence, Laplacian; Section 2.3)
  * are applied to them.  The report's own language bindings wrap each C++
  * method in one C function taking plain pointers (Section 4.1, Figure 3);
  * this header keeps that pattern: only C types, plain host or device

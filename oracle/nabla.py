@@ -1,7 +1,7 @@
 """Nabla operators on node-column fields (oracle; test infrastructure only).
 
 The paper lists gradient, divergence, curl and Laplacian among the operations
-Atlas supplies (Section 2.3) without formulas; the edge-based median-dual
+the library offers (Section 2.3) without formulas; the edge-based median-dual
 finite-volume form used here is:
 
 * gradient:   G_i = (1/V_i) [ sum_{e at i} sign(i,e) 0.5 (f_a + f_b) S_e
