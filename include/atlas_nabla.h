@@ -396,11 +396,12 @@ int atlas_batch_create(atlas_mesh_t mesh, int dtype, const atlas_tracer_desc_t* 
  * above: in the persistent form one launch per operator (as many workgroups
  * as the CUs hold at once, each walking its XCD's share of the (tracer,
  * tile, chunk) items); with batch_mode 2 the single-field launch of every
- * tracer for each operator.  An FP32 plan whose divergence and gradient
- * adjoint take the same input field in every tracer, with no output of
- * either overlapping an input, runs those two as one persistent launch on
- * the divergence's shape (as atlas_nabla_divergence_gradient_adjoint: the
- * same values); atlas_batch_tune still times them one at a time.  The
+ * tracer for each operator.  A plan whose divergence and gradient adjoint
+ * take the same input field in every tracer, with no output of either
+ * overlapping an input, runs those two as one persistent launch on the
+ * divergence's shape (as atlas_nabla_divergence_gradient_adjoint: the same
+ * values; in FP64 only on shapes of at most 8 waves, else as two launches);
+ * atlas_batch_tune still times them one at a time.  The
  * persistent form
  * allocates nothing and never synchronises; the field form does so only the
  * first time a (operator, dtype, level count) is used on the mesh, when it

@@ -1220,9 +1220,6 @@ int plan_op(atlas_batch_s* b, int o, BatchOp& bo, bool pair = false) {
 // divergence of every tracer precedes every gradient adjoint; in one pass
 // they interleave).
 bool plan_pairs(const atlas_batch_s* b) {
-  // FP32 plans only: the FP64 pair of more than one slice per step does not
-  // fit the batched kernel's 128 registers
-  if (b->dtype != ATLAS_F32) return false;
   if ((b->mask & ((1u << OP_DIV) | (1u << OP_GRADT))) != ((1u << OP_DIV) | (1u << OP_GRADT))) return false;
   const size_t es = dtype_size(b->dtype);
   const int64_t V = b->mesh->host.V;

@@ -1322,8 +1322,15 @@ __global__ __launch_bounds__((kTileThreads<S, OP, U>)) void k_tile(TileArgs a, i
 // without a memset.  Each tracer's chunk is its own (at most its tiling's), with the
 // slice count of the single-field launch (at most UMAX).  Every wave of a
 // workgroup runs the same loop, so the barriers are reached by all.
+// Workgroup size bound of the batched kernel: 1024 threads (16 waves), or
+// 512 (8 waves, up to 256 registers a lane) for the FP64 divergence pair,
+// whose two coefficient rows do not fit in 128 registers.
+template <class S, int OP>
+constexpr int kBatchedThreads = (sizeof(S) == 8 && OP == OP_DIVCURL) ? 512 : 1024;
+inline int batched_max_waves(int kop, int dtype) { return (dtype == DT_F64 && kop == OP_DIVCURL) ? 8 : 16; }
+
 template <class S, int OP, int UMAX>
-__global__ __launch_bounds__(1024) void k_tile_batched(TileArgs base, const BatchTile* __restrict__ tr,
+__global__ __launch_bounds__((kBatchedThreads<S, OP>)) void k_tile_batched(TileArgs base, const BatchTile* __restrict__ tr,
                                                        const int32_t* __restrict__ pre, int ntr,
                                                        int32_t* __restrict__ ctr, int32_t claim) {
   extern __shared__ __align__(16) char lds[];
@@ -2697,9 +2704,7 @@ const void* tb_fn(int op, int umax) {
     case OP_DIV: return tb_fn_u<S, OP_DIV>(umax);
     case OP_GRADT: return tb_fn_u<S, OP_GRADT>(umax);
     case OP_DIVT: return tb_fn_u<S, OP_DIVT>(umax);
-    case OP_DIVCURL:   // FP32 only (FP64 pairs exceed 128 registers)
-      if constexpr (std::is_same<S, float>::value) return tb_fn_u<S, OP_DIVCURL>(umax);
-      else return nullptr;
+    case OP_DIVCURL: return tb_fn_u<S, OP_DIVCURL>(umax);
     default: return nullptr;
   }
 }
@@ -2722,10 +2727,7 @@ hipError_t launch_tb_t(int op, const TileArgs& a, const BatchTile* tr, const int
     case OP_DIV: return launch_tb_u<S, OP_DIV>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
     case OP_GRADT: return launch_tb_u<S, OP_GRADT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
     case OP_DIVT: return launch_tb_u<S, OP_DIVT>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
-    case OP_DIVCURL:
-      if constexpr (std::is_same<S, float>::value)
-        return launch_tb_u<S, OP_DIVCURL>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
-      else return hipErrorInvalidValue;
+    case OP_DIVCURL: return launch_tb_u<S, OP_DIVCURL>(a, tr, pre, ntr, ctr, claim, lds, waves, grid, umax, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2735,7 +2737,7 @@ hipError_t launch_tb_t(int op, const TileArgs& a, const BatchTile* tr, const int
 int tiles_batched_per_cu(int op, int dtype, uint32_t lds, int waves, int umax) {
   const int kop = kernel_op(op);
   const void* fn = dtype == DT_F64 ? tb_fn<double>(kop, umax) : dtype == DT_F32 ? tb_fn<float>(kop, umax) : nullptr;
-  if (!fn || waves < 1 || waves > 16 || lds > kLdsPerCu || umax < 1 || umax > 3) return 0;
+  if (!fn || waves < 1 || waves > batched_max_waves(kop, dtype) || lds > kLdsPerCu || umax < 1 || umax > 3) return 0;
   if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -2752,13 +2754,13 @@ hipError_t launch_tiles_batched(int op, int dtype, const BatchTile* tr, const in
                                 int32_t claim, uint32_t lds, int waves, int64_t grid, int umax,
                                 hipStream_t stream) {
   const int kop = kernel_op(op);
-  // the four batchable operators and, in FP32, the divergence and gradient
-  // adjoint pair (each tracer's out2 set)
-  if (kop != OP_GRAD && kop != OP_DIV && kop != OP_GRADT && kop != OP_DIVT && !(op == OP_DIVGRADT && dtype == DT_F32))
+  // the four batchable operators and the divergence and gradient adjoint
+  // pair (each tracer's out2 set)
+  if (kop != OP_GRAD && kop != OP_DIV && kop != OP_GRADT && kop != OP_DIVT && op != OP_DIVGRADT)
     return hipErrorInvalidValue;
   // the grid is a multiple of 8 workgroups (one share per XCD)
   if (ntr < 1 || !ctr || claim < 1 || claim > 64 || grid < 8 || grid % 8 != 0 || grid > INT32_MAX || waves < 1 ||
-      waves > 16 || lds > kLdsPerCu || umax < 1 || umax > 3)
+      waves > batched_max_waves(kop, dtype) || lds > kLdsPerCu || umax < 1 || umax > 3)
     return hipErrorInvalidValue;
   TileArgs a;   // fields, tiling and level chunking per tracer in the kernel
   a.info = nullptr;

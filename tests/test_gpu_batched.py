@@ -95,22 +95,24 @@ def test_graph_replays_equal_eager(mode):
         tracers[0]["gradient"][0].mul_(2.0)
 
 
-def _shared_tracers(mesh, levels, seed):
+def _shared_tracers(mesh, levels, seed, dtype=torch.float32):
     """Tracers whose divergence and gradient adjoint take the same vector
     field (the plan runs them as one pass), the rest as in _tracers."""
-    tracers = _tracers(mesh, levels, torch.float32, seed)
+    tracers = _tracers(mesh, levels, dtype, seed)
     for tr in tracers:
         tr["gradient_adjoint"] = (tr["divergence"][0], tr["gradient_adjoint"][1])
     return tracers
 
 
 @pytest.mark.parametrize("mode", ["persistent", "persistent_shaped", "persistent_claim8", "fields"])
-def test_batched_divergence_gradient_adjoint_pairs(mode):
-    # FP32 plans whose divergence and gradient adjoint read the same fields:
-    # one persistent launch for both (or the field launches), eager and
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batched_divergence_gradient_adjoint_pairs(dtype, mode):
+    # plans whose divergence and gradient adjoint read the same fields: one
+    # persistent launch for both (FP64: on shapes of at most 8 waves, so the
+    # 16-wave shape runs two launches), or the field launches; eager and
     # replayed, bitwise the single-field calls
     M = pa.Mesh("O32", device=0)
-    tracers = _shared_tracers(M, [1, 19, 60, 91, 137, 137, 5, 33, 2, 64], 11)
+    tracers = _shared_tracers(M, [1, 19, 60, 91, 137, 137, 5, 33, 2, 64], 11, dtype)
     plan = pa.Batch(M, tracers, tune=MODES[mode])
     for launch in (plan.run, plan.graph_launch, plan.graph_launch):
         for tr in tracers:
