@@ -163,6 +163,16 @@ def test_describe_names_the_one_pass_kernels():
         assert pa.describe(M, op, dt, L)[1] == name, (op, dt, L)
     shape = pa.describe(M, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 137)[0]
     assert (shape["tile_kb"], shape["waves_per_block"]) == (80, 16)
+    shape = pa.describe(M, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F64, 137)[0]
+    assert (shape["tile_kb"], shape["waves_per_block"]) == (160, 8)
+    # BF16 1-ring operators: 16-wave workgroups (80 KiB for vector input,
+    # 64 KiB for scalar input); the single divergence keeps its own shape
+    for op, kb in ((pa.OP_DIVERGENCE, 80), (pa.OP_GRADIENT_ADJOINT, 80), (pa.OP_GRADIENT, 64),
+                   (pa.OP_DIVERGENCE_ADJOINT, 64)):
+        shape = pa.describe(M, op, pa.BF16, 137)[0]
+        assert (shape["tile_kb"], shape["waves_per_block"]) == (kb, 16), op
+    shape = pa.describe(M, pa.OP_DIVERGENCE, pa.F32, 137)[0]
+    assert (shape["tile_kb"], shape["waves_per_block"]) == (64, 8)
     # the pairs read the divergence's shape entry
     pa.set_tune(M, pa.OP_DIVERGENCE, pa.F32, dict(lds_tiles=2))
     assert pa.describe(M, pa.OP_DIVERGENCE_GRADIENT_ADJOINT, pa.F32, 137)[1] == "two calls"
